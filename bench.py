@@ -1,0 +1,142 @@
+"""Benchmark: truss-decomposed edges/s on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rmat20]
+
+A step is one whole truss decomposition (edge ids, orientation, support, every
+level scan and sub-level, output) of one synthetic graph that is already resident
+in device memory, through the library's C ABI with input validation off (the input
+is validated once, outside the timed region, and the result is checked against the
+stored oracle expectation when one exists).  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOADS = {
+    "er4096": "Erdos-Renyi G(n=4096, mean degree 16), seed 1",
+    "rmat20": "R-MAT scale 20, edge factor 16, (a,b,c,d)=(0.57,0.19,0.19,0.05), symmetrized, dedup, "
+              "self-loops removed, ids permuted, seed 1",
+    "rmat24": "R-MAT scale 24, edge factor 16, same recipe, seed 1",
+    "chunglu23": "Chung-Lu n=2^23, exponent 2.1, ~1e8 edges, 200 planted cliques of 50..500, seed 1",
+}
+
+
+def sha(a):
+    return hashlib.sha256(np.ascontiguousarray(a, np.int32).tobytes()).hexdigest()
+
+
+def cpu_baseline(sample_name="rmat16"):
+    """The CPU oracle (serial bucket peel, one thread) on a bounded sample of the same recipe."""
+    import graphgen as gg
+    import oracle
+
+    g = gg.workload(sample_name, seed=1)
+    t0 = time.perf_counter()
+    oracle.truss(g)
+    dt = time.perf_counter() - t0
+    return {"value": g.m / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": f"{sample_name}: R-MAT scale 16, edge factor 16, same (a,b,c,d) recipe, seed 1 "
+                      f"(m={g.m}); one full serial decomposition, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rmat20", choices=sorted(WORKLOADS))
+    ap.add_argument("--variant", default="auto")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); "
+              "multi-GPU sharding is described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import graphgen as gg
+    import paper_1707_02000_amd as pkt
+
+    pkt.load()
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    g = gg.workload(args.workload, seed=1)
+    gen_s = time.perf_counter() - t0
+    print(f"bench: {args.workload} n={g.n} m={g.m} generated in {gen_s:.1f}s", file=sys.stderr, flush=True)
+    off = torch.from_numpy(g.offsets).cuda()
+    adj = torch.from_numpy(g.adj).cuda()
+    ws = pkt.Workspace.for_graph(g.n, len(g.adj))
+    out = torch.empty(max(g.m, 1), dtype=torch.int32, device="cuda")
+
+    # untimed: validation + parity against the stored oracle result
+    tau, st0 = pkt.truss_decompose(off, adj, validate=True, variant=args.variant, workspace=ws, out=out,
+                                   return_stats=True)
+    tau_h = tau.cpu().numpy()
+    parity = None
+    gold = os.path.join(ROOT, "tests", "golden", f"{args.workload}.json")
+    if os.path.exists(gold):
+        rec = json.load(open(gold))
+        parity = rec["csr_sha256"] == g.sha256() and rec["trussness_sha256"] == sha(tau_h)
+    print(f"bench: first run stats {st0} parity={parity}", file=sys.stderr, flush=True)
+
+    def step():
+        return pkt.truss_decompose(off, adj, validate=False, variant=args.variant, workspace=ws, out=out,
+                                   return_stats=True)[1]
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms = dt * 1000.0 / args.steps
+    value = g.m / (ms / 1000.0)
+    phases = {k: round(float(np.mean([s[k] for s in stats])), 3)
+              for k in ("ms_build", "ms_support", "ms_peel", "ms_total")}
+    deg = g.degrees()
+    line = {
+        "metric": "truss-decomposed edges/s",
+        "value": value,
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "description": WORKLOADS[args.workload], "n": g.n, "m": g.m,
+                   "variant": args.variant},
+        "parity_vs_oracle": parity,
+        "wedges_per_s": pkt.wedges(deg) / (ms / 1000.0),
+        "t_max": st0["t_max"],
+        "levels": st0["levels"],
+        "sublevels": st0["sublevels"],
+        "phases_ms": phases,
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

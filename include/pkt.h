@@ -1,0 +1,202 @@
+/*
+ * pkt.h -- C ABI of libpkt, a GPU (MI355X / gfx950) truss decomposition library.
+ *
+ * The operation (Kabir and Madduri, "Shared-memory Graph Truss Decomposition",
+ * arXiv:1707.02000, Background section): for a simple undirected graph G, the
+ * support S(e) of an edge is the number of triangles containing it; the k-truss
+ * is the largest subgraph in which every edge lies in at least k-2 triangles of
+ * the subgraph; the trussness of an edge is the largest k whose k-truss contains
+ * it.  Truss decomposition is the trussness of every edge.
+ *
+ * The method (PKT section, Algorithms 3-5): support by oriented triangle
+ * counting with edge ids, then level-synchronous peeling -- for l = 0, 1, ...
+ * the edges with support l form a frontier; every frontier edge intersects the
+ * adjacency of its endpoints and lowers the support of the other two edges of
+ * each triangle still present (floored at l, a triangle with two frontier edges
+ * handled by the lower edge id only); edges reaching l form the next frontier,
+ * until no edge is left.  trussness = final support + 2.
+ *
+ * Conventions for every entry point
+ *   - Pointers named "device" are HIP device pointers; all others are host.
+ *   - Input CSR: offsets[0] = 0, offsets non-decreasing, offsets[n] = 2m; every
+ *     row strictly ascending (sorted, no duplicates); ids in [0, n); no
+ *     self-loops; symmetric ((u,v) present iff (v,u) present).  Any number of
+ *     connected components and isolated vertices.  m <= 2^31 - 1.
+ *   - Edge order of every output: edge e is the e-th pair (u, v), u < v, in
+ *     row-major order of the input CSR (rows ascending, then columns
+ *     ascending) -- the lexicographic order of the pairs.
+ *   - Ownership: the caller allocates and owns every buffer (inputs, outputs,
+ *     workspace).  The library allocates no device memory, frees nothing and
+ *     keeps no pointer after a call returns.
+ *   - Work runs on `stream` (a hipStream_t; NULL = the default stream).  Calls
+ *     return when the result is complete on that stream.  Calls with distinct
+ *     workspaces may run concurrently.
+ *   - Errors are returned as truss_status codes, never raised or aborted.  On
+ *     error the output contents are unspecified but nothing outside the given
+ *     buffers is written.  truss_last_error() gives a message for the calling
+ *     thread's last error.
+ */
+#ifndef PKT_H_
+#define PKT_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TRUSS_OK = 0,
+  TRUSS_E_ARG = 1,           /* bad argument: NULL pointer, negative size, bad option */
+  TRUSS_E_NOT_SIMPLE = 2,    /* a row is not strictly ascending, or has a self-loop */
+  TRUSS_E_NOT_SYMMETRIC = 3, /* (u, v) present without (v, u) */
+  TRUSS_E_RANGE = 4,         /* vertex id outside [0, n), bad offsets, or m too large */
+  TRUSS_E_WORKSPACE = 5,     /* workspace too small or misaligned (needs 256-byte alignment) */
+  TRUSS_E_DEVICE = 6,        /* a HIP call failed; see truss_last_error() */
+  TRUSS_E_INTERNAL = 7       /* iteration bound exceeded (a level or sub-level watchdog) */
+} truss_status;
+
+/* Intersection kernel used by the peeling sub-levels.  Every choice gives the
+ * same trussness; only the running time differs. */
+typedef enum {
+  TRUSS_VARIANT_AUTO = 0,    /* built-in heuristic per sub-level */
+  TRUSS_VARIANT_BSEARCH = 1, /* one lane per entry of the shorter row, binary search in the longer */
+  TRUSS_VARIANT_MERGE = 2,   /* one wave per frontier edge, merge of the two rows */
+  TRUSS_VARIANT_LDS = 3,     /* longer row staged in LDS, shorter row probed there */
+  TRUSS_VARIANT_LEARNED = 4  /* MLP cost model (truss_options.mlp_weights) picks per sub-level */
+} truss_variant;
+
+/* One record per launch sequence of the peeling loop (when tracing). */
+typedef struct {
+  int32_t level;             /* support level at the start */
+  int32_t kind;              /* 0 level scan, 1 fused small-frontier launch, 2 wide frontier */
+  int32_t variant;           /* truss_variant used for kinds 1 and 2 */
+  int32_t rounds;            /* frontier rounds completed by the sequence */
+  int64_t frontier;          /* frontier size at the start */
+  int64_t items;             /* intersection items of the first round (kind 2), else -1 */
+  float ms;                  /* device time of the sequence */
+  float features[8];         /* cost-model features at the start (truss_features order) */
+  int32_t pad;
+} truss_trace_record;
+
+/* Host-side trace buffer: the library appends up to `capacity` records and
+ * sets `count`.  Tracing runs the host-driven loop with one sync per sequence. */
+typedef struct {
+  int64_t capacity;
+  int64_t count;
+  truss_trace_record* records;
+} truss_trace;
+
+typedef struct {
+  int32_t variant;           /* truss_variant; default AUTO */
+  int32_t device_loop;       /* 1 = device-driven sub-level loop replayed as a hipGraph (default 1) */
+  int32_t validate;          /* 1 = check the input CSR before any other work (default 1) */
+  int32_t owner_rule;        /* 0 = the lower edge id owns a two-frontier-edge triangle (the
+                                paper's rule, default); 1 = the higher id (the paper's stated
+                                alternative); for tests, the output does not change */
+  int32_t compact;           /* 1 = periodically drop peeled edges from the working adjacency
+                                (default 1); 0 = intersect the full rows every time */
+  int32_t steps_per_sync;    /* device-driven loop: sub-level steps per host check (0 = auto) */
+  const float* mlp_weights;  /* device: weights for TRUSS_VARIANT_LEARNED (truss_mlp_weights_floats
+                                floats), or NULL */
+  truss_trace* trace;        /* host: per-sequence trace of the peeling loop, or NULL */
+  int32_t reserved[6];       /* must be zero */
+} truss_options;
+
+typedef struct {
+  int64_t m;             /* edges */
+  int64_t levels;        /* levels scanned (non-empty and skipped-to) */
+  int64_t sublevels;     /* frontier rounds */
+  int64_t triangles;     /* triangles in the input graph */
+  int32_t t_max;         /* maximum trussness (0 when m = 0) */
+  int32_t compactions;   /* adjacency rebuilds */
+  float ms_validate;     /* phase times (ms, device events) */
+  float ms_build;        /* edge ids, orientation */
+  float ms_support;
+  float ms_peel;         /* level loop: scans, sub-levels, compactions */
+  float ms_total;
+  int64_t variant_count[5]; /* sub-levels run with each truss_variant */
+} truss_stats;
+
+/* Fills *opt with the defaults listed above. */
+void truss_default_options(truss_options* opt);
+
+/* Workspace bytes needed by truss_decompose for a graph with n vertices and
+ * two_m adjacency slots (= offsets[n]).  opt may be NULL (defaults). */
+truss_status truss_workspace_bytes(int32_t n, int64_t two_m, const truss_options* opt, size_t* bytes);
+
+/*
+ * Trussness of every edge of one graph.
+ *   n           vertices (>= 0)
+ *   offsets     device, int64[n+1]
+ *   adj         device, int32[offsets[n]]
+ *   trussness   device, int32[m] output, m = offsets[n] / 2, edge order as above
+ *   workspace   device, >= truss_workspace_bytes(...) bytes, 256-byte aligned;
+ *               contents on entry are ignored
+ *   opt         NULL = defaults
+ *   stats       NULL or host struct receiving counters and phase times
+ *   stream      hipStream_t (NULL = default stream)
+ * Input is validated first when opt->validate is set; with validate = 0 the input
+ * must satisfy the contract above (the library then reads only offsets[0..n] and
+ * adj[0..offsets[n]) but its results are unspecified for a malformed CSR).
+ */
+truss_status truss_decompose(int32_t n, const int64_t* offsets, const int32_t* adj, int32_t* trussness,
+                             void* workspace, size_t workspace_bytes, const truss_options* opt,
+                             truss_stats* stats, void* stream);
+
+/* Same as truss_decompose for int32 offsets (requires offsets[n] <= 2^31 - 1).
+ * Needs truss_workspace_bytes(n, two_m) + 8 * (n + 1) bytes, rounded up to 256. */
+truss_status truss_decompose32(int32_t n, const int32_t* offsets, const int32_t* adj, int32_t* trussness,
+                               void* workspace, size_t workspace_bytes, const truss_options* opt,
+                               truss_stats* stats, void* stream);
+
+/*
+ * Initial support of every edge (number of triangles containing it), same
+ * edge order, into support (device, int32[m]).  Same workspace as
+ * truss_decompose.
+ */
+truss_status truss_support(int32_t n, const int64_t* offsets, const int32_t* adj, int32_t* support,
+                           void* workspace, size_t workspace_bytes, const truss_options* opt, void* stream);
+
+/* Endpoints of every edge in output order: el_u[e] < el_v[e] (device, int32[m]
+ * each).  Same workspace as truss_decompose. */
+truss_status truss_edge_list(int32_t n, const int64_t* offsets, const int32_t* adj, int32_t* el_u,
+                             int32_t* el_v, void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Batched decomposition of many independent small graphs in one persistent
+ * launch (each workgroup takes whole graphs from a queue, largest first).
+ *   num_graphs       G >= 0
+ *   graph_vtx_off    device, int64[G+1]: the offsets of graph g occupy
+ *                    offsets_packed[graph_vtx_off[g] .. graph_vtx_off[g+1]), i.e.
+ *                    n_g + 1 entries
+ *   graph_adj_off    device, int64[G+1]: the adjacency of graph g occupies
+ *                    adj_packed[graph_adj_off[g] .. graph_adj_off[g+1]), i.e. 2 m_g
+ *                    entries
+ *   offsets_packed   device, int32: local offsets of each graph (start at 0)
+ *   adj_packed       device, int32: local vertex ids
+ *   trussness_packed device, int32[sum m_g]: graph g's edges at graph_adj_off[g] / 2 + e
+ * Each graph must satisfy the CSR contract with n_g <= 2^20 and m_g <= 2^24.
+ * Workspace: truss_batched_workspace_bytes with the same sizes.
+ */
+truss_status truss_batched_workspace_bytes(int32_t num_graphs, int64_t total_vtx_entries, int64_t total_adj,
+                                           const truss_options* opt, size_t* bytes);
+truss_status truss_decompose_batched(int32_t num_graphs, const int64_t* graph_vtx_off,
+                                     const int64_t* graph_adj_off, const int32_t* offsets_packed,
+                                     const int32_t* adj_packed, int32_t* trussness_packed,
+                                     int64_t total_vtx_entries, int64_t total_adj, void* workspace,
+                                     size_t workspace_bytes, const truss_options* opt, truss_stats* stats,
+                                     void* stream);
+
+/* Static message for a status code. */
+const char* truss_strerror(truss_status status);
+
+/* Message for the calling thread's most recent error (empty if none). */
+const char* truss_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PKT_H_ */

@@ -1,0 +1,334 @@
+"""Python binding of libpkt, a gfx950 (MI355X) truss decomposition library.
+
+Argument marshalling only: every step of the computation runs in the HIP kernels of
+``libpkt.so`` (``csrc/``), reached through its C ABI (``include/pkt.h``).  PyTorch
+provides device memory and the stream.  There is no CPU fallback: if the library
+is missing or no GPU is visible, calls raise.
+
+    import paper_1707_02000_amd as pkt
+    tau = pkt.truss_decompose(offsets, adj)      # int32 trussness per edge, on the GPU
+
+Edge order of every per-edge output: the pairs (u, v), u < v, in row-major order
+of the input CSR.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpkt.so")
+
+VARIANTS = {"auto": 0, "bsearch": 1, "merge": 2, "lds": 3, "learned": 4}
+
+STATUS = {
+    0: "TRUSS_OK", 1: "TRUSS_E_ARG", 2: "TRUSS_E_NOT_SIMPLE", 3: "TRUSS_E_NOT_SYMMETRIC",
+    4: "TRUSS_E_RANGE", 5: "TRUSS_E_WORKSPACE", 6: "TRUSS_E_DEVICE", 7: "TRUSS_E_INTERNAL",
+}
+
+
+class TrussError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.name = STATUS.get(code, str(code))
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("variant", ctypes.c_int32),
+        ("device_loop", ctypes.c_int32),
+        ("validate", ctypes.c_int32),
+        ("owner_rule", ctypes.c_int32),
+        ("compact", ctypes.c_int32),
+        ("steps_per_sync", ctypes.c_int32),
+        ("mlp_weights", ctypes.c_void_p),
+        ("trace", ctypes.c_void_p),
+        ("reserved", ctypes.c_int32 * 6),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("m", ctypes.c_int64),
+        ("levels", ctypes.c_int64),
+        ("sublevels", ctypes.c_int64),
+        ("triangles", ctypes.c_int64),
+        ("t_max", ctypes.c_int32),
+        ("compactions", ctypes.c_int32),
+        ("ms_validate", ctypes.c_float),
+        ("ms_build", ctypes.c_float),
+        ("ms_support", ctypes.c_float),
+        ("ms_peel", ctypes.c_float),
+        ("ms_total", ctypes.c_float),
+        ("variant_count", ctypes.c_int64 * 5),
+    ]
+
+    def as_dict(self) -> dict:
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "variant_count"}
+        d["variant_count"] = list(self.variant_count)
+        return d
+
+
+class TraceRecord(ctypes.Structure):
+    _fields_ = [
+        ("level", ctypes.c_int32),
+        ("kind", ctypes.c_int32),
+        ("variant", ctypes.c_int32),
+        ("rounds", ctypes.c_int32),
+        ("frontier", ctypes.c_int64),
+        ("items", ctypes.c_int64),
+        ("ms", ctypes.c_float),
+        ("features", ctypes.c_float * 8),
+        ("pad", ctypes.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("features", "pad")}
+        d["features"] = list(self.features)
+        return d
+
+
+class Trace(ctypes.Structure):
+    _fields_ = [("capacity", ctypes.c_int64), ("count", ctypes.c_int64),
+                ("records", ctypes.POINTER(TraceRecord))]
+
+
+_lib = None
+
+# exported C functions and their signatures
+_SIGS = {
+    "truss_default_options": (None, [ctypes.c_void_p]),
+    "truss_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
+    "truss_decompose": (ctypes.c_int, [ctypes.c_int32] + [ctypes.c_void_p] * 4 + [ctypes.c_size_t]
+                        + [ctypes.c_void_p] * 3),
+    "truss_decompose32": (ctypes.c_int, [ctypes.c_int32] + [ctypes.c_void_p] * 4 + [ctypes.c_size_t]
+                          + [ctypes.c_void_p] * 3),
+    "truss_support": (ctypes.c_int, [ctypes.c_int32] + [ctypes.c_void_p] * 4 + [ctypes.c_size_t]
+                      + [ctypes.c_void_p] * 2),
+    "truss_edge_list": (ctypes.c_int, [ctypes.c_int32] + [ctypes.c_void_p] * 5 + [ctypes.c_size_t]
+                        + [ctypes.c_void_p]),
+    "truss_batched_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
+                                                     ctypes.c_void_p, ctypes.c_void_p]),
+    "truss_decompose_batched": (ctypes.c_int, [ctypes.c_int32] + [ctypes.c_void_p] * 5
+                                + [ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t]
+                                + [ctypes.c_void_p] * 3),
+    "truss_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "truss_last_error": (ctypes.c_char_p, []),
+}
+
+
+def load():
+    """Load libpkt.so (built by ``paper_1707_02000_amd.build``); raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libpkt.so not built at {LIB_PATH}; run __graft_entry__.build() "
+                          "(python -m paper_1707_02000_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(code: int):
+    if code != 0:
+        msg = load().truss_last_error().decode(errors="replace")
+        raise TrussError(code, msg)
+
+
+def default_options() -> Options:
+    o = Options()
+    load().truss_default_options(ctypes.byref(o))
+    return o
+
+
+def make_options(variant="auto", device_loop=True, validate=True, owner_rule=0, compact=True,
+                 steps_per_sync=0, mlp_weights=None) -> Options:
+    o = default_options()
+    o.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+    o.device_loop = int(bool(device_loop))
+    o.validate = int(bool(validate))
+    o.owner_rule = int(owner_rule)
+    o.compact = int(bool(compact))
+    o.steps_per_sync = int(steps_per_sync)
+    o.mlp_weights = None if mlp_weights is None else ctypes.c_void_p(mlp_weights.data_ptr())
+    return o
+
+
+def _torch():
+    import torch
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible: libpkt runs only on the GPU")
+    return torch
+
+
+def _dev(x, dtype, torch):
+    if isinstance(x, np.ndarray):
+        x = torch.from_numpy(np.ascontiguousarray(x))
+    x = x.to(device="cuda", dtype=dtype)
+    return x.contiguous()
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p(0)
+
+
+def _stream(torch, stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def alloc_workspace(nbytes: int):
+    """Device workspace of nbytes, 256-byte aligned (over-allocates and offsets if needed)."""
+    torch = _torch()
+    buf = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device="cuda")
+    shift = (-buf.data_ptr()) % 256
+    return buf, buf.data_ptr() + shift
+
+
+def workspace_bytes(n: int, two_m: int, options: Options | None = None) -> int:
+    nb = ctypes.c_size_t(0)
+    _check(load().truss_workspace_bytes(int(n), int(two_m), ctypes.byref(options) if options else None,
+                                        ctypes.byref(nb)))
+    return nb.value
+
+
+@dataclass
+class Workspace:
+    """A reusable device workspace for graphs up to (n, two_m)."""
+
+    n: int
+    two_m: int
+    buf: object
+    ptr: int
+    nbytes: int
+
+    @classmethod
+    def for_graph(cls, n: int, two_m: int, batched: bool = False, num_graphs: int = 0):
+        lib = load()
+        nb = ctypes.c_size_t(0)
+        if batched:
+            _check(lib.truss_batched_workspace_bytes(int(num_graphs), int(n), int(two_m), None, ctypes.byref(nb)))
+        else:
+            _check(lib.truss_workspace_bytes(int(n), int(two_m), None, ctypes.byref(nb)))
+        buf, ptr = alloc_workspace(nb.value)
+        return cls(n, two_m, buf, ptr, nb.value)
+
+
+def truss_decompose(offsets, adj, *, variant="auto", device_loop=True, validate=True, owner_rule=0,
+                    compact=True, steps_per_sync=0, mlp_weights=None, stream=None, workspace=None,
+                    out=None, return_stats=False, trace_capacity=0):
+    """Trussness (int32, >= 2) of every edge of a simple undirected CSR graph, on the GPU.
+
+    offsets: int64 (or int32) [n+1]; adj: int32 [2m]; numpy arrays (copied to the GPU) or
+    CUDA tensors.  Returns a CUDA int32 tensor [m] (and a stats dict if return_stats; with
+    trace_capacity > 0 the stats dict also holds the per-sequence trace of the peeling loop).
+    """
+    torch = _torch()
+    lib = load()
+    off32 = (isinstance(offsets, np.ndarray) and offsets.dtype == np.int32) or \
+            (hasattr(offsets, "dtype") and str(offsets.dtype) == "torch.int32")
+    off_t = _dev(offsets, torch.int32 if off32 else torch.int64, torch)
+    adj_t = _dev(adj, torch.int32, torch)
+    n = off_t.numel() - 1
+    two_m = adj_t.numel()
+    m = two_m // 2
+    opt = make_options(variant, device_loop, validate, owner_rule, compact, steps_per_sync, mlp_weights)
+    if workspace is None:
+        nb = workspace_bytes(n, two_m, opt) + (8 * (n + 1) + 256 if off32 else 0)
+        _buf, wptr = alloc_workspace(nb)
+    else:
+        _buf, wptr, nb = workspace.buf, workspace.ptr, workspace.nbytes
+    if out is None:
+        out = torch.empty(max(m, 1), dtype=torch.int32, device="cuda")
+    st = Stats()
+    trace = None
+    if trace_capacity > 0:
+        recs = (TraceRecord * int(trace_capacity))()
+        trace = Trace(int(trace_capacity), 0, ctypes.cast(recs, ctypes.POINTER(TraceRecord)))
+        opt.trace = ctypes.cast(ctypes.pointer(trace), ctypes.c_void_p)
+    fn = lib.truss_decompose32 if off32 else lib.truss_decompose
+    code = fn(n, _ptr(off_t), _ptr(adj_t), _ptr(out), ctypes.c_void_p(wptr), nb, ctypes.byref(opt),
+              ctypes.byref(st), _stream(torch, stream))
+    _check(code)
+    res = out[:m]
+    sd = st.as_dict()
+    if trace is not None:
+        sd["trace"] = [recs[i].as_dict() for i in range(trace.count)]
+    return (res, sd) if return_stats else res
+
+
+def truss_support(offsets, adj, *, stream=None):
+    """Initial support (triangles per edge), int32 [m] CUDA tensor, computed on the GPU."""
+    torch = _torch()
+    lib = load()
+    off_t = _dev(offsets, torch.int64, torch)
+    adj_t = _dev(adj, torch.int32, torch)
+    n, two_m = off_t.numel() - 1, adj_t.numel()
+    nb = workspace_bytes(n, two_m)
+    _buf, wptr = alloc_workspace(nb)
+    out = torch.empty(max(two_m // 2, 1), dtype=torch.int32, device="cuda")
+    _check(lib.truss_support(n, _ptr(off_t), _ptr(adj_t), _ptr(out), ctypes.c_void_p(wptr), nb, None,
+                             _stream(torch, stream)))
+    return out[: two_m // 2]
+
+
+def edge_list(offsets, adj, *, stream=None):
+    """Endpoints of every edge in output order, (m, 2) int32 CUDA tensor (u < v)."""
+    torch = _torch()
+    lib = load()
+    off_t = _dev(offsets, torch.int64, torch)
+    adj_t = _dev(adj, torch.int32, torch)
+    n, two_m = off_t.numel() - 1, adj_t.numel()
+    m = two_m // 2
+    nb = workspace_bytes(n, two_m)
+    _buf, wptr = alloc_workspace(nb)
+    eu = torch.empty(max(m, 1), dtype=torch.int32, device="cuda")
+    ev = torch.empty(max(m, 1), dtype=torch.int32, device="cuda")
+    _check(lib.truss_edge_list(n, _ptr(off_t), _ptr(adj_t), _ptr(eu), _ptr(ev), ctypes.c_void_p(wptr), nb,
+                               _stream(torch, stream)))
+    return torch.stack([eu[:m], ev[:m]], dim=1)
+
+
+def truss_decompose_batched(vtx_off, adj_off, offsets_packed, adj_packed, *, variant="auto", validate=True,
+                            stream=None, workspace=None, out=None, return_stats=False):
+    """Trussness of many packed graphs (layout of include/pkt.h); int32 [sum m_g] CUDA tensor."""
+    torch = _torch()
+    lib = load()
+    vo = _dev(vtx_off, torch.int64, torch)
+    ao = _dev(adj_off, torch.int64, torch)
+    op = _dev(offsets_packed, torch.int32, torch)
+    ap = _dev(adj_packed, torch.int32, torch)
+    G = vo.numel() - 1
+    total_vtx, total_adj = int(op.numel()), int(ap.numel())
+    opt = make_options(variant, True, validate)
+    if workspace is None:
+        nb = ctypes.c_size_t(0)
+        _check(lib.truss_batched_workspace_bytes(G, total_vtx, total_adj, ctypes.byref(opt), ctypes.byref(nb)))
+        nb = nb.value
+        _buf, wptr = alloc_workspace(nb)
+    else:
+        _buf, wptr, nb = workspace.buf, workspace.ptr, workspace.nbytes
+    if out is None:
+        out = torch.empty(max(total_adj // 2, 1), dtype=torch.int32, device="cuda")
+    st = Stats()
+    _check(lib.truss_decompose_batched(G, _ptr(vo), _ptr(ao), _ptr(op), _ptr(ap), _ptr(out), total_vtx, total_adj,
+                                       ctypes.c_void_p(wptr), nb, ctypes.byref(opt), ctypes.byref(st),
+                                       _stream(torch, stream)))
+    res = out[: total_adj // 2]
+    return (res, st.as_dict()) if return_stats else res
+
+
+def wedges(degrees: np.ndarray) -> int:
+    """Wedge count (sum of d(d-1)/2), the paper's work measure for its GWeps rate."""
+    d = np.asarray(degrees, dtype=np.int64)
+    return int((d * (d - 1) // 2).sum())

@@ -1,0 +1,148 @@
+// Shared helpers of libpkt: types, error reporting, wave/block primitives for
+// CDNA (wave64), workspace carving.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stdio.h>
+
+#include "../../include/pkt.h"
+
+typedef int64_t i64;
+typedef int32_t i32;
+typedef uint32_t u32;
+typedef uint64_t u64;
+typedef uint8_t u8;
+
+#define PKT_WAVE 64
+#define PKT_BLOCK 256  // 4 waves
+
+// Edge states of the peeling (the paper's inCurr / inNext / processed, packed).
+enum : u8 { ST_ALIVE = 0, ST_CURR = 1, ST_NEXT = 2, ST_PROC = 3 };
+
+// Validation error bits.
+enum : u32 { VERR_RANGE = 1u, VERR_NOT_SIMPLE = 2u, VERR_NOT_SYMMETRIC = 4u };
+
+// ---------------------------------------------------------------- host errors
+namespace pkt {
+void set_error(const char* fmt, ...);
+truss_status hip_fail(hipError_t e, const char* what, const char* file, int line);
+}  // namespace pkt
+
+#define PKT_HIP(call)                                                      \
+  do {                                                                     \
+    hipError_t e_ = (call);                                                \
+    if (e_ != hipSuccess) return pkt::hip_fail(e_, #call, __FILE__, __LINE__); \
+  } while (0)
+
+#define PKT_LAUNCH_CHECK() PKT_HIP(hipGetLastError())
+
+// ------------------------------------------------------------ device helpers
+
+// First index in [lo, hi) with a[idx] >= x (hi if none).
+template <class T, class I>
+__device__ __forceinline__ I lower_bound_dev(const T* __restrict__ a, I lo, I hi, T x) {
+  while (lo < hi) {
+    I mid = lo + ((hi - lo) >> 1);
+    if (a[mid] < x)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// First index in [lo, hi) with a[idx] > x (hi if none).
+template <class T, class I>
+__device__ __forceinline__ I upper_bound_dev(const T* __restrict__ a, I lo, I hi, T x) {
+  while (lo < hi) {
+    I mid = lo + ((hi - lo) >> 1);
+    if (a[mid] <= x)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (PKT_WAVE - 1)); }
+
+// Wave-aggregated append: every lane with pred gets a distinct slot of
+// out[*counter ...]; one atomic per wave.  Must be reached by all active lanes.
+__device__ __forceinline__ i32 wave_append_slot(bool pred, i32* counter) {
+  u64 mask = __ballot(pred);
+  if (mask == 0) return -1;
+  const int lane = lane_id();
+  const int leader = __ffsll((unsigned long long)mask) - 1;
+  i32 base = 0;
+  if (lane == leader) base = atomicAdd(counter, (i32)__popcll(mask));
+  base = __shfl(base, leader);
+  return pred ? base + (i32)__popcll(mask & ((1ull << lane) - 1ull)) : -1;
+}
+
+__device__ __forceinline__ i64 wave_sum_i64(i64 v) {
+  for (int o = PKT_WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+__device__ __forceinline__ i32 wave_min_i32(i32 v) {
+  for (int o = PKT_WAVE / 2; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+  return v;
+}
+
+__device__ __forceinline__ i32 wave_max_i32(i32 v) {
+  for (int o = PKT_WAVE / 2; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+  return v;
+}
+
+// Inclusive scan within a wave.
+__device__ __forceinline__ i64 wave_incl_scan_i64(i64 v) {
+  const int lane = lane_id();
+  for (int o = 1; o < PKT_WAVE; o <<= 1) {
+    i64 y = __shfl_up(v, o);
+    if (lane >= o) v += y;
+  }
+  return v;
+}
+
+// Exclusive scan over a block of NT threads.  `tmp` is LDS of NT / PKT_WAVE
+// entries.  Returns the exclusive prefix; *total gets the block sum.  All
+// threads must call it.
+template <int NT = PKT_BLOCK>
+__device__ __forceinline__ i64 block_excl_scan_i64(i64 v, i64* tmp, i64* total) {
+  const int lane = lane_id(), wid = threadIdx.x / PKT_WAVE;
+  i64 inc = wave_incl_scan_i64(v);
+  if (lane == PKT_WAVE - 1) tmp[wid] = inc;
+  __syncthreads();
+  i64 pre = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < NT / PKT_WAVE; ++w) {
+    i64 t = tmp[w];
+    pre += (w < wid) ? t : 0;
+    tot += t;
+  }
+  __syncthreads();
+  *total = tot;
+  return pre + inc - v;
+}
+
+__device__ __forceinline__ i32 atomic_load_relaxed(const i32* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ------------------------------------------------------------ host helpers
+
+static inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Sequential carving of one workspace buffer into 256-byte aligned pieces.
+struct Carver {
+  char* base;
+  size_t used;
+  explicit Carver(void* b) : base((char*)b), used(0) {}
+  template <class T>
+  T* take(size_t count) {
+    T* p = base ? (T*)(base + used) : nullptr;
+    used += align_up(count * sizeof(T) + 1, 256);
+    return p;
+  }
+};

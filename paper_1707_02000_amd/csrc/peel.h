@@ -1,0 +1,37 @@
+// Peeling (level loop) shared definitions.
+#pragma once
+#include "truss.h"
+
+#define SCAN_ITEMS 16        // alive-list entries per thread per tile of a level scan
+#define SMALL_FRONTIER 2048  // frontiers up to this size run as one fused launch
+#define SMALL_THREADS 512    // threads per block of the fused launch
+#define SMALL_BLOCKS 256     // blocks of the fused launch
+#define ALONE_FRONTIER 512   // the fused launch's last block goes on alone on frontiers up to this size,
+#define ALONE_ITEMS 4096     // with at most this many intersection items,
+#define ALONE_ALIVE 32768    // and scans alone when the alive list is at most this long
+#define GALLOP_K 8           // short-row entries per item when galloping
+#define GALLOP_RATIO 32      // AUTO gallops when the longer row is at most this many times the shorter
+
+// Everything a peeling kernel touches.
+struct PeelArgs {
+  Ctl* ctl;
+  i32* F0;
+  i32* F1;
+  i32* A0;
+  i32* A1;
+  const int2* el;
+  CsrSet csr;
+  i32* S;
+  u8* state;
+  int owner_higher;
+};
+
+namespace pkt {
+CsrSet csr_set(const Work& w);
+truss_status validate_input(const Work& w, hipStream_t s);
+truss_status build_edges(const Work& w, hipStream_t s);
+truss_status compute_support(const Work& w, hipStream_t s);
+truss_status init_peel(const Work& w, hipStream_t s);
+truss_status compact(const Work& w, hipStream_t s);
+truss_status write_output(const Work& w, i32* out, hipStream_t s);
+}  // namespace pkt

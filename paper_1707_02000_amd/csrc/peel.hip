@@ -1,0 +1,667 @@
+// Level-synchronous peeling on gfx950 (Kabir and Madduri, arXiv:1707.02000,
+// PKT section: Algorithm 4 -- level scan and sub-level loop; Algorithm 5 --
+// sub-level processing; the text on concurrent triangle processing and on
+// reducing concurrent array additions).
+//
+// Kernels (each reads the control block at entry and returns at once when the
+// loop state says it has nothing to do):
+//   k_scan_level  level scan over the alive list, block-aggregated appends
+//   k_psl_small   a whole sub-level of a frontier of <= SMALL_FRONTIER edges in
+//                 one launch: every block builds the frontier's work prefix in
+//                 LDS and takes a share of the intersection items; the last block
+//                 to finish marks the states, swaps the frontiers, and goes on
+//                 alone through further tiny frontiers and short level scans
+//   k_psl_bsearch + k_finalize  wide sub-level after a device-wide scan of the
+//                 per-edge work (scan.h)
+#include <limits.h>
+#include <string.h>
+
+#include "peel.h"
+#include "scan.h"
+
+namespace {
+
+// Decrement rule for edge x of a triangle whose other non-frontier-edge is y,
+// seen from frontier edge e1: x loses one unit if its support is above l and e1
+// owns the triangle (y is not in the frontier, or e1 has the lower id -- the
+// higher id with owner_higher).  The atomic's old value decides: l + 1 means x
+// now sits at l and joins the next frontier; <= l means the decrement overshot
+// (another thread got there first) and is undone.  Returns x if it joined the
+// next frontier, else -1.  The plain pre-read of S may be stale: while S[x] > l
+// every older value is > l too, and once S[x] <= l it stays <= l for the level,
+// so a stale read can only cause a decrement that is then undone.
+__device__ __forceinline__ i32 psl_rule(i32 x, i32 y, i32 e1, i32 l, i32* S, u8* state, int owner_higher) {
+  if (atomic_load_relaxed(&S[x]) <= l) return -1;
+  const bool y_curr = state[y] == ST_CURR;
+  const bool mine = !y_curr || (owner_higher ? (e1 > y) : (e1 < y));
+  if (!mine) return -1;
+  const i32 a = atomicSub(&S[x], 1);
+  if (a == l + 1) {
+    state[x] = ST_NEXT;
+    return x;
+  }
+  if (a <= l) atomicAdd(&S[x], 1);
+  return -1;
+}
+
+// Shorter and longer working rows of frontier edge e1 = (u, v).
+struct Rows {
+  i64 sb, slen, lb, le;
+};
+
+__device__ __forceinline__ Rows rows_of(const Csr& c, int2 uv) {
+  const i64 ub = c.off[uv.x], ue = c.off[uv.x + 1], vb = c.off[uv.y], ve = c.off[uv.y + 1];
+  Rows r;
+  if (ue - ub <= ve - vb) {
+    r.sb = ub; r.slen = ue - ub; r.lb = vb; r.le = ve;
+  } else {
+    r.sb = vb; r.slen = ve - vb; r.lb = ub; r.le = ue;
+  }
+  return r;
+}
+
+// Entries of the shorter row handled by one item.  One binary search places
+// the first entry in the longer row; the rest gallop forward from there (a
+// merge that skips), which pays off when the rows have similar lengths.
+__device__ __forceinline__ i64 chunk_of(int variant, i64 slen, i64 llen) {
+  if (variant == TRUSS_VARIANT_BSEARCH) return 1;
+  if (variant == TRUSS_VARIANT_MERGE) return GALLOP_K;
+  return (llen <= GALLOP_RATIO * slen) ? GALLOP_K : 1;  // AUTO: per edge, by row-length ratio
+}
+
+// Work of a frontier edge at level l (items): the shorter working row in chunks;
+// nothing at level 0 (a frontier edge at level l lies in at most l triangles
+// whose edges are all unprocessed).
+__device__ __forceinline__ i64 work_of(const PeelArgs& a, const Csr& c, i32 e1, i32 l, int variant) {
+  if (l == 0) return 0;
+  const Rows r = rows_of(c, a.el[e1]);
+  const i64 k = chunk_of(variant, r.slen, r.le - r.lb);
+  return (r.slen + k - 1) / k;
+}
+
+// First index q in [p, le) with B[q] >= w: exponential steps from p, then a
+// binary search inside the last step.
+__device__ __forceinline__ i64 gallop(const i32* __restrict__ B, i64 p, i64 le, i32 w) {
+  i64 lo = p, step = 1, hi;
+  for (;;) {
+    hi = lo + step - 1;
+    if (hi >= le) {
+      hi = le;
+      break;
+    }
+    if (B[hi] >= w) {
+      hi += 1;
+      break;
+    }
+    lo = hi + 1;
+    step <<= 1;
+  }
+  return lower_bound_dev(B, lo, hi, w);
+}
+
+// Triangle {u, v, w} seen from frontier edge e1, whose other two edges are es
+// and eo: unless one of them is processed, applies the decrement rule to both.
+__device__ __forceinline__ void psl_triangle(const PeelArgs& a, i32 e1, i32 es, i32 eo, i32 l, i32& y0, i32& y1) {
+  if (a.state[es] == ST_PROC || a.state[eo] == ST_PROC) return;
+  y0 = psl_rule(es, eo, e1, l, a.S, a.state, a.owner_higher);
+  y1 = psl_rule(eo, es, e1, l, a.S, a.state, a.owner_higher);
+}
+
+// Item t of frontier edge e1: chunk t of the shorter row, located in the
+// longer row.  Edges that reached l come back in x0, x1 for a wave-aggregated
+// append; when one item produces more than two, the extra ones are appended at
+// once through spill_ctr.
+__device__ __forceinline__ void psl_item(const PeelArgs& a, const Csr& c, i32 e1, i64 t, i32 l, int variant,
+                                         i32& x0, i32& x1, i32* spill_next, i32* spill_ctr) {
+  const Rows r = rows_of(c, a.el[e1]);
+  const i64 k = chunk_of(variant, r.slen, r.le - r.lb);
+  const i64 j0 = r.sb + t * k, j1 = min(r.sb + r.slen, j0 + k);
+  i64 p = r.lb;
+  for (i64 j = j0; j < j1; ++j) {
+    const i32 w = c.adj[j];
+    p = (j == j0) ? lower_bound_dev(c.adj, p, r.le, w) : gallop(c.adj, p, r.le, w);
+    if (p == r.le) break;
+    if (c.adj[p] != w) continue;
+    i32 y0 = -1, y1 = -1;
+    psl_triangle(a, e1, c.eid[j], c.eid[p], l, y0, y1);
+    if (y0 >= 0) {
+      if (x0 < 0) x0 = y0; else if (x1 < 0) x1 = y0; else spill_next[atomicAdd(spill_ctr, 1)] = y0;
+    }
+    if (y1 >= 0) {
+      if (x0 < 0) x0 = y1; else if (x1 < 0) x1 = y1; else spill_next[atomicAdd(spill_ctr, 1)] = y1;
+    }
+    ++p;
+  }
+}
+
+__device__ __forceinline__ void append_next(i32 x0, i32 x1, i32* next, i32* counter) {
+  const i32 s0 = wave_append_slot(x0 >= 0, counter);
+  if (x0 >= 0) next[s0] = x0;
+  const i32 s1 = wave_append_slot(x1 >= 0, counter);
+  if (x1 >= 0) next[s1] = x1;
+}
+
+// Control-block update after a sub-level: frontier processed, next frontier
+// current, buffers swapped, an empty next frontier ends the level.
+__device__ __forceinline__ void ctl_after_sublevel(Ctl* ctl, i32 nc, i32 nn, i32 sel) {
+  ctl->processed += nc;
+  ctl->ncurr = nn;
+  ctl->nnext = 0;
+  ctl->sel = sel ^ 1;
+  ctl->sublevels += 1;
+  if (nn == 0) ctl->level += 1;
+}
+
+// Control-block update after a level scan: the found edges form the frontier;
+// if none were found, jump to the lowest support left, or finish.
+__device__ __forceinline__ void ctl_after_scan(Ctl* ctl, i32 nfound, i32 nkeep, i32 minabove, i32 asel) {
+  ctl->ncurr = nfound;
+  ctl->nfound = 0;
+  ctl->nalive = nkeep;
+  ctl->nalive_out = 0;
+  ctl->asel = asel ^ 1;
+  ctl->levels += 1;
+  if (nfound == 0) {
+    if (nkeep == 0)
+      ctl->done = 1;
+    else
+      ctl->level = minabove;
+  }
+  ctl->min_above = INT_MAX;
+}
+
+// Level scan over tiles of the alive list (tiles tile0, tile0 + tstride, ...):
+// edges still unprocessed with support l join the frontier and turn CURR;
+// other unprocessed edges are copied to the other alive list; processed edges
+// drop out.  One atomic per counter per tile of NT * SCAN_ITEMS entries.
+template <int NT>
+__device__ void scan_tiles(const PeelArgs& a, i32 l, i32 na, const i32* __restrict__ A, i32* __restrict__ Aout,
+                           i32* __restrict__ curr, i64 tile0, i64 tstride, i32& mn, i64* tmp, i32* sbase) {
+  const i64 tile = (i64)NT * SCAN_ITEMS;
+  for (i64 t0 = tile0 * tile; t0 < na; t0 += tstride * tile) {
+    u32 tk = 0, kp = 0;
+    i32 ev[SCAN_ITEMS];
+    u8 st[SCAN_ITEMS];
+    i32 sv[SCAN_ITEMS];
+    // all loads first (no branch between them), then classify
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+      const i64 i = t0 + (i64)k * NT + threadIdx.x;
+      ev[k] = (i < na) ? A[i] : -1;
+    }
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+      const i32 e = ev[k] < 0 ? 0 : ev[k];
+      st[k] = a.state[e];
+      sv[k] = a.S[e];
+    }
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+      if (ev[k] >= 0 && st[k] == ST_ALIVE) {
+        if (sv[k] == l) {
+          tk |= 1u << k;
+        } else {
+          kp |= 1u << k;
+          mn = min(mn, sv[k]);
+        }
+      }
+    }
+    const i64 packed = ((i64)__popc(tk) << 32) | (i64)__popc(kp);
+    i64 tot;
+    const i64 ex = block_excl_scan_i64<NT>(packed, tmp, &tot);
+    if (threadIdx.x == 0) {
+      const i32 nt = (i32)(tot >> 32), nk = (i32)(tot & 0xffffffffll);
+      sbase[0] = nt ? atomicAdd(&a.ctl->nfound, nt) : 0;
+      sbase[1] = nk ? atomicAdd(&a.ctl->nalive_out, nk) : 0;
+    }
+    __syncthreads();
+    i32 pt = sbase[0] + (i32)(ex >> 32), pk = sbase[1] + (i32)(ex & 0xffffffffll);
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+      if ((tk >> k) & 1u) {
+        curr[pt++] = ev[k];
+        a.state[ev[k]] = ST_CURR;
+      } else if ((kp >> k) & 1u) {
+        Aout[pk++] = ev[k];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Marks the end of a sub-level: frontier edges processed, next ones current.
+__device__ __forceinline__ void mark_states(const PeelArgs& a, const i32* curr, i32 nc, const i32* next, i32 nn,
+                                            i64 tid, i64 stride) {
+  for (i64 i = tid; i < nc; i += stride) a.state[curr[i]] = ST_PROC;
+  for (i64 i = tid; i < nn; i += stride) a.state[next[i]] = ST_CURR;
+}
+
+// Exclusive prefix of the work of frontier edges [0, nc) into LDS P[0..nc]
+// (nc <= SMALL_FRONTIER); returns the total.  Every thread of the block calls it.
+template <int NT>
+__device__ i64 lds_work_prefix(const PeelArgs& a, const Csr& c, const i32* curr, i32 nc, i32 l, int variant,
+                                i64* P, i64* tmp) {
+  constexpr int PER = SMALL_FRONTIER / NT;
+  const int i0 = threadIdx.x * PER;
+  i64 w[PER];
+  i64 sum = 0;
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int i = i0 + k;
+    w[k] = (i < nc) ? work_of(a, c, curr[i], l, variant) : 0;
+    sum += w[k];
+  }
+  i64 tot;
+  i64 run = block_excl_scan_i64<NT>(sum, tmp, &tot);
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int i = i0 + k;
+    if (i < nc) P[i] = run;
+    run += w[k];
+  }
+  if (threadIdx.x == 0) P[nc] = tot;
+  __syncthreads();
+  return tot;
+}
+
+// Items [base, total) with the given stride, pairs located through LDS P.
+template <int NT>
+__device__ void lds_items(const PeelArgs& a, const Csr& c, const i32* curr, i32 nc, i32 l, int variant, const i64* P,
+                          i64 total, i64 base, i64 stride, i32* next) {
+  for (i64 b = base; b < total; b += stride) {
+    const i64 g = b + threadIdx.x;
+    i32 x0 = -1, x1 = -1;
+    if (g < total) {
+      const i64 i = upper_bound_dev(P, (i64)0, (i64)nc + 1, g) - 1;
+      psl_item(a, c, curr[i], g - P[i], l, variant, x0, x1, next, &a.ctl->nnext);
+    }
+    append_next(x0, x1, next, &a.ctl->nnext);
+  }
+}
+
+// Snapshot of the control block shared through LDS by one block.
+struct CtlView {
+  i32 done, ncurr, level, sel, csel, nalive, asel, variant;
+};
+
+__device__ __forceinline__ void load_view(const Ctl* ctl, CtlView* v) {
+  if (threadIdx.x == 0) {
+    v->done = ctl->done;
+    v->ncurr = ctl->ncurr;
+    v->level = ctl->level;
+    v->sel = ctl->sel;
+    v->csel = ctl->csel;
+    v->nalive = ctl->nalive;
+    v->asel = ctl->asel;
+    v->variant = ctl->variant;
+  }
+  __syncthreads();
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(PKT_BLOCK) void k_scan_level(PeelArgs a) {
+  Ctl* ctl = a.ctl;
+  if (ctl->done || ctl->ncurr != 0) return;
+  const i32 l = ctl->level, na = ctl->nalive, asel = ctl->asel;
+  const i32* A = asel ? a.A1 : a.A0;
+  i32* Aout = asel ? a.A0 : a.A1;
+  i32* curr = ctl->sel ? a.F1 : a.F0;
+  __shared__ i64 tmp[PKT_BLOCK / PKT_WAVE];
+  __shared__ i32 sbase[2];
+  __shared__ int last;
+  i32 mn = INT_MAX;
+  scan_tiles<PKT_BLOCK>(a, l, na, A, Aout, curr, blockIdx.x, gridDim.x, mn, tmp, sbase);
+  mn = wave_min_i32(mn);
+  if (lane_id() == 0 && mn != INT_MAX) atomicMin(&ctl->min_above, mn);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    last = (atomicAdd(&ctl->arrive, 1u) == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (last && threadIdx.x == 0) {
+    __threadfence();
+    ctl_after_scan(ctl, atomicAdd(&ctl->nfound, 0), atomicAdd(&ctl->nalive_out, 0),
+                   atomicAdd(&ctl->min_above, 0), asel);
+    ctl->arrive = 0;
+  }
+}
+
+__global__ __launch_bounds__(SMALL_THREADS) void k_psl_small(PeelArgs a) {
+  Ctl* ctl = a.ctl;
+  __shared__ i64 P[SMALL_FRONTIER + 1];
+  __shared__ i64 tmp[SMALL_THREADS / PKT_WAVE];
+  __shared__ i32 sbase[2];
+  __shared__ CtlView v;
+  __shared__ int last;
+  __shared__ i32 s_nn;
+  load_view(ctl, &v);
+  if (v.done || v.ncurr == 0 || v.ncurr > SMALL_FRONTIER) return;
+  {
+    const i32 nc = v.ncurr, l = v.level, sel = v.sel;
+    const Csr c = a.csr.pick(v.csel);
+    const i32* curr = sel ? a.F1 : a.F0;
+    i32* next = sel ? a.F0 : a.F1;
+    const i64 total = lds_work_prefix<SMALL_THREADS>(a, c, curr, nc, l, v.variant, P, tmp);
+    lds_items<SMALL_THREADS>(a, c, curr, nc, l, v.variant, P, total, (i64)blockIdx.x * SMALL_THREADS,
+                             (i64)gridDim.x * SMALL_THREADS, next);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __threadfence();
+      last = (atomicAdd(&ctl->arrive, 1u) == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();  // see every block's supports, states and appends
+    if (threadIdx.x == 0) s_nn = atomicAdd(&ctl->nnext, 0);
+    __syncthreads();
+    const i32 nn = s_nn;
+    mark_states(a, curr, nc, next, nn, threadIdx.x, SMALL_THREADS);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      ctl_after_sublevel(ctl, nc, nn, sel);
+      ctl->arrive = 0;
+    }
+    __syncthreads();
+  }
+  // The last block goes on alone while the work stays small: tiny frontiers,
+  // and level scans over a short alive list.
+  for (int iter = 0; iter < (1 << 20); ++iter) {
+    load_view(ctl, &v);
+    if (v.done) break;
+    const i32 l = v.level, sel = v.sel;
+    i32* curr = (i32*)(sel ? a.F1 : a.F0);
+    if (v.ncurr == 0) {
+      if (v.nalive > ALONE_ALIVE) break;
+      const i32* A = v.asel ? a.A1 : a.A0;
+      i32* Aout = v.asel ? a.A0 : a.A1;
+      i32 mn = INT_MAX;
+      scan_tiles<SMALL_THREADS>(a, l, v.nalive, A, Aout, curr, 0, 1, mn, tmp, sbase);
+      mn = wave_min_i32(mn);
+      if (lane_id() == 0 && mn != INT_MAX) atomicMin(&ctl->min_above, mn);
+      __syncthreads();
+      if (threadIdx.x == 0)
+        ctl_after_scan(ctl, atomicAdd(&ctl->nfound, 0), atomicAdd(&ctl->nalive_out, 0),
+                       atomicAdd(&ctl->min_above, 0), v.asel);
+      __syncthreads();
+      continue;
+    }
+    if (v.ncurr > ALONE_FRONTIER) break;
+    const Csr c = a.csr.pick(v.csel);
+    i32* next = (i32*)(sel ? a.F0 : a.F1);
+    const i64 total = lds_work_prefix<SMALL_THREADS>(a, c, curr, v.ncurr, l, v.variant, P, tmp);
+    if (total > ALONE_ITEMS) break;
+    lds_items<SMALL_THREADS>(a, c, curr, v.ncurr, l, v.variant, P, total, 0, SMALL_THREADS, next);
+    __syncthreads();
+    if (threadIdx.x == 0) s_nn = atomicAdd(&ctl->nnext, 0);
+    __syncthreads();
+    mark_states(a, curr, v.ncurr, next, s_nn, threadIdx.x, SMALL_THREADS);
+    __syncthreads();
+    if (threadIdx.x == 0) ctl_after_sublevel(ctl, v.ncurr, s_nn, sel);
+    __syncthreads();
+  }
+}
+
+// Work of frontier edge i for the device-wide scan (wide frontiers).
+struct WideLen {
+  PeelArgs a;
+  __device__ bool active() const {
+    const Ctl* c = a.ctl;
+    return !c->done && c->ncurr > SMALL_FRONTIER && c->level > 0;
+  }
+  __device__ i64 count() const { return a.ctl->ncurr; }
+  __device__ i64 len(i64 i) const {
+    const Ctl* c = a.ctl;
+    const i32* curr = c->sel ? a.F1 : a.F0;
+    return work_of(a, a.csr.pick(c->csel), curr[i], c->level, c->variant);
+  }
+};
+
+__global__ __launch_bounds__(PKT_BLOCK) void k_psl_bsearch(WideLen f, const i64* __restrict__ P) {
+  if (!f.active()) return;
+  const PeelArgs& a = f.a;
+  Ctl* ctl = a.ctl;
+  __shared__ i64 sp[2];
+  const i64 npairs = ctl->ncurr;
+  const i64 total = P[npairs];
+  const i32 l = ctl->level;
+  const int variant = ctl->variant;
+  const i32* curr = ctl->sel ? a.F1 : a.F0;
+  i32* next = ctl->sel ? a.F0 : a.F1;
+  const Csr c = a.csr.pick(ctl->csel);
+  for (i64 base = (i64)blockIdx.x * PKT_BLOCK; base < total; base += (i64)gridDim.x * PKT_BLOCK) {
+    if (threadIdx.x == 0) sp[0] = upper_bound_dev(P, (i64)0, npairs + 1, base) - 1;
+    if (threadIdx.x == PKT_WAVE)
+      sp[1] = upper_bound_dev(P, (i64)0, npairs + 1, min(base + PKT_BLOCK, total) - 1) - 1;
+    __syncthreads();
+    const i64 g = base + threadIdx.x;
+    i32 x0 = -1, x1 = -1;
+    if (g < total) {
+      const i64 i = upper_bound_dev(P, sp[0], sp[1] + 1, g) - 1;
+      psl_item(a, c, curr[i], g - P[i], l, variant, x0, x1, next, &ctl->nnext);
+    }
+    append_next(x0, x1, next, &ctl->nnext);
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(PKT_BLOCK) void k_finalize(PeelArgs a) {
+  Ctl* ctl = a.ctl;
+  if (ctl->done || ctl->ncurr <= SMALL_FRONTIER) return;
+  const i32 nc = ctl->ncurr, nn = ctl->nnext, sel = ctl->sel;
+  const i32* curr = sel ? a.F1 : a.F0;
+  const i32* next = sel ? a.F0 : a.F1;
+  mark_states(a, curr, nc, next, nn, (i64)blockIdx.x * PKT_BLOCK + threadIdx.x, (i64)gridDim.x * PKT_BLOCK);
+  __shared__ int last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    last = (atomicAdd(&ctl->arrive, 1u) == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (last && threadIdx.x == 0) {
+    __threadfence();
+    ctl_after_sublevel(ctl, nc, nn, sel);
+    ctl->arrive = 0;
+  }
+}
+
+// ------------------------------------------------------------------ host side
+
+namespace pkt {
+
+namespace {
+
+inline int grid_for(i64 count, int cap) {
+  i64 g = (count + PKT_BLOCK - 1) / PKT_BLOCK;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+struct Timer {
+  hipEvent_t ev[8];
+  int k = 0;
+  bool on = false;
+  hipStream_t s;
+  void init(bool enable, hipStream_t st) {
+    on = enable;
+    s = st;
+    if (on)
+      for (int i = 0; i < 8; ++i) (void)hipEventCreate(&ev[i]);
+  }
+  void mark() {
+    if (on && k < 8) (void)hipEventRecord(ev[k++], s);
+  }
+  float ms(int a, int b) {
+    float t = 0.f;
+    if (on && b < k) (void)hipEventElapsedTime(&t, ev[a], ev[b]);
+    return t;
+  }
+  ~Timer() {
+    if (on)
+      for (int i = 0; i < 8; ++i) (void)hipEventDestroy(ev[i]);
+  }
+};
+
+thread_local Ctl* h_ctl_pinned = nullptr;
+
+truss_status read_ctl(const Work& w, Ctl* out, hipStream_t s) {
+  if (!h_ctl_pinned) PKT_HIP(hipHostMalloc((void**)&h_ctl_pinned, sizeof(Ctl), hipHostMallocDefault));
+  PKT_HIP(hipMemcpyAsync(h_ctl_pinned, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+  PKT_HIP(hipStreamSynchronize(s));
+  *out = *h_ctl_pinned;
+  return TRUSS_OK;
+}
+
+}  // namespace
+
+PeelArgs peel_args(const Work& w, const truss_options& opt) {
+  PeelArgs a;
+  a.ctl = w.ctl;
+  a.F0 = w.F[0];
+  a.F1 = w.F[1];
+  a.A0 = w.A[0];
+  a.A1 = w.A[1];
+  a.el = w.el;
+  a.csr = csr_set(w);
+  a.S = w.S;
+  a.state = w.state;
+  a.owner_higher = opt.owner_rule == 1;
+  return a;
+}
+
+// One launch sequence for the current loop state (the state was read into hc).
+static truss_status launch_round(const Work& w, const PeelArgs& a, const Ctl& hc, hipStream_t s, int* kind) {
+  if (hc.ncurr == 0) {
+    *kind = 0;
+    hipLaunchKernelGGL(k_scan_level, dim3(grid_for(((i64)hc.nalive + SCAN_ITEMS - 1) / SCAN_ITEMS, 2048)),
+                       dim3(PKT_BLOCK), 0, s, a);
+  } else if (hc.ncurr <= SMALL_FRONTIER) {
+    *kind = 1;
+    hipLaunchKernelGGL(k_psl_small, dim3(SMALL_BLOCKS), dim3(SMALL_THREADS), 0, s, a);
+  } else {
+    *kind = 2;
+    WideLen f{a};
+    PKT_HIP(scan_launch(f, w.partial, w.X, s));
+    hipLaunchKernelGGL(k_psl_bsearch, dim3(2048), dim3(PKT_BLOCK), 0, s, f, (const i64*)w.X);
+    hipLaunchKernelGGL(k_finalize, dim3(grid_for(hc.ncurr, 1024)), dim3(PKT_BLOCK), 0, s, a);
+  }
+  PKT_LAUNCH_CHECK();
+  return TRUSS_OK;
+}
+
+truss_status run_single(const Work& w, const truss_options& opt, truss_stats* stats, i32* trussness,
+                        hipStream_t s, bool support_only) {
+  Timer tm;
+  tm.init(stats != nullptr, s);
+  tm.mark();  // 0
+  Ctl init;
+  memset(&init, 0, sizeof(init));
+  init.min_above = INT_MAX;
+  init.nalive = (i32)w.m;
+  init.csr_edges = (i32)w.m;
+  init.variant = (opt.variant == TRUSS_VARIANT_BSEARCH || opt.variant == TRUSS_VARIANT_MERGE) ? opt.variant
+                                                                                          : TRUSS_VARIANT_AUTO;
+  PKT_HIP(hipMemcpyAsync(w.ctl, &init, sizeof(Ctl), hipMemcpyHostToDevice, s));
+  if (opt.validate) {
+    truss_status st = validate_input(w, s);
+    if (st) return st;
+  }
+  tm.mark();  // 1
+  if (w.m == 0) {
+    if (stats) memset(stats, 0, sizeof(*stats));
+    PKT_HIP(hipStreamSynchronize(s));
+    return TRUSS_OK;
+  }
+  truss_status st = build_edges(w, s);
+  if (st) return st;
+  tm.mark();  // 2
+  st = compute_support(w, s);
+  if (st) return st;
+  tm.mark();  // 3
+  if (support_only) {
+    PKT_HIP(hipMemcpyAsync(trussness, w.S, (size_t)w.m * sizeof(i32), hipMemcpyDeviceToDevice, s));
+    PKT_HIP(hipStreamSynchronize(s));
+    return TRUSS_OK;
+  }
+  st = init_peel(w, s);
+  if (st) return st;
+  const PeelArgs a = peel_args(w, opt);
+  truss_trace* trace = opt.trace;
+  hipEvent_t tev[2];
+  if (trace) {
+    PKT_HIP(hipEventCreate(&tev[0]));
+    PKT_HIP(hipEventCreate(&tev[1]));
+  }
+  Ctl hc;
+  st = read_ctl(w, &hc, s);
+  if (st) return st;
+  i64 guard = 0;
+  const i64 guard_max = 4 * w.m + 4096;
+  while (!hc.done) {
+    if (++guard > guard_max) {
+      set_error("level / sub-level count exceeded its bound");
+      return TRUSS_E_INTERNAL;
+    }
+    if (opt.compact && hc.ncurr == 0 && (i64)(w.m - hc.processed) * 2 < (i64)hc.csr_edges) {
+      st = compact(w, s);
+      if (st) return st;
+      st = read_ctl(w, &hc, s);
+      if (st) return st;
+    }
+    const Ctl before = hc;
+    int kind = 0;
+    if (trace) PKT_HIP(hipEventRecord(tev[0], s));
+    st = launch_round(w, a, hc, s, &kind);
+    if (st) return st;
+    if (trace) PKT_HIP(hipEventRecord(tev[1], s));
+    st = read_ctl(w, &hc, s);
+    if (st) return st;
+    if (trace && trace->count < trace->capacity) {
+      truss_trace_record& r = trace->records[trace->count++];
+      memset(&r, 0, sizeof(r));
+      r.level = before.level;
+      r.kind = kind;
+      r.variant = kind == 0 ? 0 : before.variant;
+      r.rounds = hc.sublevels - before.sublevels;
+      r.frontier = before.ncurr;
+      r.items = -1;
+      if (kind == 2) PKT_HIP(hipMemcpy(&r.items, w.X + before.ncurr, sizeof(i64), hipMemcpyDeviceToHost));
+      PKT_HIP(hipEventElapsedTime(&r.ms, tev[0], tev[1]));
+    }
+  }
+  if (trace) {
+    (void)hipEventDestroy(tev[0]);
+    (void)hipEventDestroy(tev[1]);
+  }
+  tm.mark();  // 4
+  st = write_output(w, trussness, s);
+  if (st) return st;
+  tm.mark();  // 5
+  st = read_ctl(w, &hc, s);
+  if (st) return st;
+  if (hc.processed != w.m) {
+    set_error("peeling ended with %lld of %lld edges processed", (long long)hc.processed, (long long)w.m);
+    return TRUSS_E_INTERNAL;
+  }
+  if (stats) {
+    memset(stats, 0, sizeof(*stats));
+    stats->m = w.m;
+    stats->levels = hc.levels;
+    stats->sublevels = hc.sublevels;
+    stats->triangles = hc.tri3 / 3;
+    stats->t_max = hc.tmax_s;
+    stats->compactions = hc.compactions;
+    stats->ms_validate = tm.ms(0, 1);
+    stats->ms_build = tm.ms(1, 2);
+    stats->ms_support = tm.ms(2, 3);
+    stats->ms_peel = tm.ms(3, 4);
+    stats->ms_total = tm.ms(0, 5);
+    stats->variant_count[hc.variant] = hc.sublevels;
+  }
+  return TRUSS_OK;
+}
+
+}  // namespace pkt

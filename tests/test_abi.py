@@ -1,0 +1,125 @@
+"""The C ABI without a GPU: the library loads, exports every declared symbol,
+host-only entry points behave, and the Python layer refuses to run without it."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pkt.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(truss_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1707_02000_amd as pkt
+
+    if not os.path.exists(pkt.LIB_PATH):
+        pytest.fail("libpkt.so is not built (run __graft_entry__.build())")
+    return pkt.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(lib, name), name
+    import paper_1707_02000_amd as pkt
+
+    out = subprocess.check_output(["nm", "-D", "--defined-only", pkt.LIB_PATH]).decode()
+    exported = set(re.findall(r"\bT (truss_\w+)", out))
+    assert set(names) == exported
+
+
+def declared_param_counts():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    out = {}
+    for name, params in re.findall(r"\b(truss_[a-z0-9_]+)\s*\(([^)]*)\)\s*;", text):
+        params = params.strip()
+        out[name] = 0 if params in ("", "void") else params.count(",") + 1
+    return out
+
+
+def test_binding_signatures_match_header(lib):
+    import paper_1707_02000_amd as pkt
+
+    counts = declared_param_counts()
+    assert set(counts) == set(pkt._SIGS)
+    for name, (_, args) in pkt._SIGS.items():
+        assert len(args) == counts[name], name
+
+
+def test_default_options_and_struct_sizes(lib):
+    import paper_1707_02000_amd as pkt
+
+    o = pkt.default_options()
+    assert (o.variant, o.device_loop, o.validate, o.owner_rule, o.compact) == (0, 1, 1, 0, 1)
+    assert ctypes.sizeof(pkt.Options) == 64
+    assert ctypes.sizeof(pkt.Stats) == 104
+
+
+def test_workspace_bytes_host_only(lib):
+    import paper_1707_02000_amd as pkt
+
+    a = pkt.workspace_bytes(1000, 20000)
+    b = pkt.workspace_bytes(1000, 40000)
+    assert 0 < a < b
+    assert a % 256 == 0
+    with pytest.raises(pkt.TrussError) as ei:
+        pkt.workspace_bytes(-1, 10)
+    assert ei.value.name == "TRUSS_E_ARG"
+    with pytest.raises(pkt.TrussError) as ei:
+        pkt.workspace_bytes(10, 7)  # odd slot count
+    assert ei.value.name == "TRUSS_E_ARG"
+    with pytest.raises(pkt.TrussError) as ei:
+        pkt.workspace_bytes(10, 2 * (2**31))  # m above 2^31 - 1
+    assert ei.value.name == "TRUSS_E_RANGE"
+
+
+def test_strerror_covers_every_status(lib):
+    for code in range(8):
+        assert lib.truss_strerror(code)
+    assert b"unknown" in lib.truss_strerror(99)
+
+
+def test_bad_arguments_rejected_before_device_work(lib):
+    # n < 0 and bad option values are rejected before any HIP call
+    import paper_1707_02000_amd as pkt
+
+    code = lib.truss_decompose(-1, None, None, None, None, 0, None, None, None)
+    assert code == 1
+    o = pkt.default_options()
+    o.variant = 42
+    code = lib.truss_decompose(4, None, None, None, None, 0, ctypes.byref(o), None, None)
+    assert code == 1
+    o = pkt.default_options()
+    o.reserved[3] = 1
+    code = lib.truss_decompose(4, None, None, None, None, 0, ctypes.byref(o), None, None)
+    assert code == 1
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    import paper_1707_02000_amd as pkt
+
+    monkeypatch.setattr(pkt, "_lib", None)
+    monkeypatch.setattr(pkt, "LIB_PATH", str(tmp_path / "nope.so"))
+    with pytest.raises(ImportError):
+        pkt.load()
+
+
+def test_product_code_never_touches_the_oracle():
+    pkg = os.path.join(ROOT, "paper_1707_02000_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"^\s*(import|from)\s+oracle\b", text, re.M), f
+                assert "wc_truss" not in text, f

@@ -1,0 +1,163 @@
+"""GPU parity: libpkt (through its C ABI) against the CPU oracle, bit for bit.
+
+All outputs are integers (edge ids, supports, trussness), so every comparison is
+exact.  Small cases run the oracle in-process; full-size workloads compare against
+stored expectations written by tests/golden/make_golden.py (oracle only).
+"""
+import hashlib
+import itertools
+import json
+import os
+import random
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from oracle import definition as D
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def gpu_tau(pkt, g, **kw):
+    return pkt.truss_decompose(g.offsets, g.adj, **kw).cpu().numpy()
+
+
+def sha(a):
+    return hashlib.sha256(np.ascontiguousarray(a, np.int32).tobytes()).hexdigest()
+
+
+def test_native_library_loaded(gpu_lib):
+    assert gpu_lib.load()._name == gpu_lib.LIB_PATH
+
+
+def small_graphs():
+    yield "K2", gg.from_edges(2, [(0, 1)])
+    for n in (3, 5, 9, 17, 40):
+        yield f"K{n}", gg.from_edges(n, itertools.combinations(range(n), 2))
+    yield "K12-e", gg.from_edges(12, [e for e in itertools.combinations(range(12), 2) if e != (0, 1)])
+    yield "wheel", gg.from_edges(9, [(0, i) for i in range(1, 9)] + [(i, i % 8 + 1) for i in range(1, 9)])
+    yield "windmill", gg.from_edges(11, sum(([(0, 2 * b + 1), (0, 2 * b + 2), (2 * b + 1, 2 * b + 2)]
+                                             for b in range(5)), []))
+    yield "path", gg.from_edges(50, [(i, i + 1) for i in range(49)])
+    yield "isolated", gg.from_edges(30, [(3, 7), (7, 9), (3, 9), (20, 21)])
+    rng = random.Random(1)
+    for i in range(40):
+        n = rng.randint(2, 40)
+        p = rng.random() ** 1.3
+        yield f"rand{i}", gg.from_edges(n, [(u, v) for u in range(n) for v in range(u + 1, n) if rng.random() < p])
+
+
+@pytest.mark.parametrize("name,g", list(small_graphs()))
+def test_small_graphs(gpu_lib, name, g):
+    say("case", name, "n", g.n, "m", g.m)
+    assert np.array_equal(gpu_tau(gpu_lib, g), oracle.truss(g))
+
+
+@pytest.mark.parametrize("make", [
+    lambda: gg.er(4096, mean_degree=16.0, seed=1),
+    lambda: gg.rmat(12, 16, seed=3),
+    lambda: gg.rgg(3000, 30.0, seed=4),
+    lambda: gg.chunglu(1 << 13, 2.1, 6.0e4, draws=55_000, ncliques=4, cmin=10, cmax=40, seed=5),
+])
+def test_support_and_edge_list(gpu_lib, make):
+    g = make()
+    say("case", g.name)
+    el = gpu_lib.edge_list(g.offsets, g.adj).cpu().numpy()
+    assert np.array_equal(el, oracle.edge_list(g))
+    S = gpu_lib.truss_support(g.offsets, g.adj).cpu().numpy()
+    assert np.array_equal(S, oracle.support(g))
+
+
+@pytest.mark.parametrize("make", [
+    lambda: gg.er(4096, mean_degree=16.0, seed=1),
+    lambda: gg.rmat(12, 16, seed=3),
+    lambda: gg.rmat(14, 16, seed=7),
+    lambda: gg.rgg(3000, 30.0, seed=4),
+    lambda: gg.chunglu(1 << 13, 2.1, 6.0e4, draws=55_000, ncliques=4, cmin=10, cmax=40, seed=5),
+])
+@pytest.mark.parametrize("opts", [
+    dict(),
+    dict(owner_rule=1),
+    dict(compact=False),
+    dict(variant="bsearch"),
+    dict(variant="merge"),
+])
+def test_medium_graphs(gpu_lib, make, opts):
+    g = make()
+    say("case", g.name, opts)
+    assert np.array_equal(gpu_tau(gpu_lib, g, **opts), oracle.truss(g))
+
+
+def test_int32_offsets(gpu_lib):
+    g = gg.rmat(11, 16, seed=2)
+    tau = gpu_lib.truss_decompose(g.offsets.astype(np.int32), g.adj).cpu().numpy()
+    assert np.array_equal(tau, oracle.truss(g))
+
+
+def test_repeatable(gpu_lib):
+    g = gg.rmat(13, 16, seed=9)
+    ref = gpu_tau(gpu_lib, g)
+    for _ in range(5):
+        assert np.array_equal(gpu_tau(gpu_lib, g), ref)
+
+
+def test_empty_and_degenerate(gpu_lib):
+    for g in (gg.from_edges(0, []), gg.from_edges(5, []), gg.from_edges(1, [])):
+        assert gpu_tau(gpu_lib, g).shape == (0,)
+    assert np.array_equal(gpu_tau(gpu_lib, gg.from_edges(2, [(0, 1)])), [2])
+
+
+def test_malformed_inputs_rejected(gpu_lib):
+    cases = {
+        "TRUSS_E_NOT_SIMPLE": ([0, 2, 4, 7, 8], [1, 2, 0, 2, 1, 0, 3, 2]),
+        "TRUSS_E_RANGE": ([0, 2, 4, 7, 8], [1, 2, 0, 9, 0, 1, 3, 2]),
+        "TRUSS_E_NOT_SYMMETRIC": ([0, 2, 4, 7, 8], [1, 3, 0, 2, 0, 1, 3, 2]),
+    }
+    for want, (off, adj) in cases.items():
+        with pytest.raises(gpu_lib.TrussError) as ei:
+            gpu_lib.truss_decompose(np.array(off, np.int64), np.array(adj, np.int32))
+        assert ei.value.name == want
+    with pytest.raises(gpu_lib.TrussError) as ei:  # self-loops on both vertices of an edge
+        gpu_lib.truss_decompose(np.array([0, 2, 4], np.int64), np.array([0, 1, 0, 1], np.int32))
+    assert ei.value.name == "TRUSS_E_NOT_SIMPLE"
+    with pytest.raises(gpu_lib.TrussError) as ei:  # odd slot count
+        gpu_lib.truss_decompose(np.array([0, 2, 3], np.int64), np.array([1, 2, 0], np.int32))
+    assert ei.value.name in ("TRUSS_E_ARG", "TRUSS_E_RANGE")
+
+
+def test_batched_matches_oracle(gpu_lib):
+    b = gg.batch(24, 64, 700, seed=11)
+    say("case batch24", b.total_m)
+    tau = gpu_lib.truss_decompose_batched(b.vtx_off, b.adj_off, b.offsets, b.adj).cpu().numpy()
+    for i in range(b.num_graphs):
+        g = b.graph(i)
+        s = int(b.adj_off[i]) // 2
+        assert np.array_equal(tau[s:s + g.m], oracle.truss(g)), i
+
+
+def _golden(name):
+    path = os.path.join(GOLDEN, f"{name}.json")
+    if not os.path.exists(path):
+        pytest.skip(f"no stored expectation for {name}")
+    return json.load(open(path))
+
+
+@pytest.mark.parametrize("name", ["er4096", "rmat16", "rmat18", "rmat20"])
+def test_full_size_against_stored_oracle(gpu_lib, name):
+    rec = _golden(name)
+    g = gg.workload(name, seed=rec["seed"])
+    assert g.sha256() == rec["csr_sha256"]
+    say("case", name, "m", g.m)
+    tau, st = gpu_lib.truss_decompose(g.offsets, g.adj, validate=False, return_stats=True)
+    tau = tau.cpu().numpy()
+    assert int(tau.max()) == rec["t_max"]
+    assert np.bincount(tau).tolist() == rec["histogram"]
+    assert sha(tau) == rec["trussness_sha256"]
+    assert st["triangles"] == rec["triangles"]
