@@ -31,8 +31,32 @@ WORKLOADS = {
 }
 
 
+METRIC = "truss-decomposed edges/s, R-MAT s20/s24; batched+learned vs plain, 1 MI355X"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+# Algorithmic bytes of the wide sub-level kernel (one item = one entry of the shorter
+# working row searched in the longer row): the entry's vertex id and edge id (8 B),
+# that edge's state byte (1 B) and the longer-row entry the search lands on (4 B);
+# per frontier edge: its id (4 B), endpoints (8 B) and four row offsets (32 B).
+BYTES_PER_ITEM = 13
+BYTES_PER_FRONTIER_EDGE = 44
+
+
 def sha(a):
     return hashlib.sha256(np.ascontiguousarray(a, np.int32).tobytes()).hexdigest()
+
+
+def measured_traffic(workload):
+    """HBM-side bytes per launch of the dominant kernel from the committed counter summary,
+    or None if there is none for this workload or the kernel's sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"k_psl_bsearch_{workload}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    fields = dict(l.split(" = ", 1) for l in open(path).read().splitlines() if " = " in l)
+    csrc = os.path.join(ROOT, "paper_1707_02000_amd", "csrc")
+    src = "".join(open(os.path.join(csrc, f)).read() for f in ("common.h", "truss.h", "peel.h", "scan.h", "peel.hip"))
+    if hashlib.sha256(src.encode()).hexdigest()[:16] != fields.get("source_sha256_16", "").strip():
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(sample_name="rmat16"):
@@ -57,7 +81,20 @@ def main():
     ap.add_argument("--workload", default="rmat20", choices=sorted(WORKLOADS))
     ap.add_argument("--variant", default="auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many MiB (5 times), to scale "
+                         "the FETCH_SIZE / WRITE_SIZE hardware counters")
     args = ap.parse_args()
+    if args.calibrate_copy_mib:
+        import torch
+
+        src = torch.ones(args.calibrate_copy_mib * (1 << 20) // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 4, "copies": 5}))
+        return
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); "
               "multi-GPU sharding is described in DESIGN.md but not built", file=sys.stderr)
@@ -95,7 +132,7 @@ def main():
 
     def step():
         return pkt.truss_decompose(off, adj, validate=False, variant=args.variant, workspace=ws, out=out,
-                                   return_stats=True)[1]
+                                   return_stats=True, profile=True)[1]
 
     for _ in range(args.warmup):
         step()
@@ -109,8 +146,25 @@ def main():
     phases = {k: round(float(np.mean([s[k] for s in stats])), 3)
               for k in ("ms_build", "ms_support", "ms_peel", "ms_total")}
     deg = g.degrees()
+    # dominant kernel: the wide sub-level intersection kernel; its launches are timed
+    # with HIP events on the library's stream inside the timed steps
+    launches = sum(s["wide_launches"] for s in stats)
+    dom_ms = sum(s["wide_ms"] for s in stats)
+    items = sum(s["wide_items"] for s in stats)
+    frontier = sum(s["wide_frontier"] for s in stats)
+    alg_bytes = BYTES_PER_ITEM * items + BYTES_PER_FRONTIER_EDGE * frontier
+    roofline = None
+    if launches and dom_ms > 0:
+        achieved = alg_bytes / launches / (dom_ms / launches / 1e3) / 1e9
+        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload),
+                    "kernel": "k_psl_bsearch", "launches_per_step": launches / args.steps,
+                    "avg_launch_us": dom_ms / launches * 1e3,
+                    "alg_bytes_per_launch": alg_bytes / launches,
+                    "model": f"{BYTES_PER_ITEM} B per shorter-row entry searched + "
+                             f"{BYTES_PER_FRONTIER_EDGE} B per frontier edge"}
     line = {
-        "metric": "truss-decomposed edges/s",
+        "metric": METRIC,
         "value": value,
         "unit": "edges/s",
         "n_gpus": 1,
@@ -130,7 +184,7 @@ def main():
         "levels": st0["levels"],
         "sublevels": st0["sublevels"],
         "phases_ms": phases,
-        "roofline": None,
+        "roofline": roofline,
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:

@@ -101,7 +101,9 @@ typedef struct {
   const float* mlp_weights;  /* device: weights for TRUSS_VARIANT_LEARNED (truss_mlp_weights_floats
                                 floats), or NULL */
   truss_trace* trace;        /* host: per-sequence trace of the peeling loop, or NULL */
-  int32_t reserved[6];       /* must be zero */
+  int32_t profile;           /* 1 = time every launch of the wide sub-level kernel with events
+                                (truss_stats.wide_ms) */
+  int32_t reserved[5];       /* must be zero */
 } truss_options;
 
 typedef struct {
@@ -117,6 +119,12 @@ typedef struct {
   float ms_peel;         /* level loop: scans, sub-levels, compactions */
   float ms_total;
   int64_t variant_count[5]; /* sub-levels run with each truss_variant */
+  /* the wide sub-level intersection kernel (the dominant kernel) */
+  int64_t wide_launches;   /* launches that found work */
+  int64_t wide_items;      /* intersection items (one per shorter-row entry searched) */
+  int64_t wide_frontier;   /* frontier edges */
+  float wide_ms;           /* summed device time of its launches (opt.profile only) */
+  int32_t pad;
 } truss_stats;
 
 /* Fills *opt with the defaults listed above. */

@@ -47,7 +47,8 @@ class Options(ctypes.Structure):
         ("steps_per_sync", ctypes.c_int32),
         ("mlp_weights", ctypes.c_void_p),
         ("trace", ctypes.c_void_p),
-        ("reserved", ctypes.c_int32 * 6),
+        ("profile", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 5),
     ]
 
 
@@ -65,10 +66,15 @@ class Stats(ctypes.Structure):
         ("ms_peel", ctypes.c_float),
         ("ms_total", ctypes.c_float),
         ("variant_count", ctypes.c_int64 * 5),
+        ("wide_launches", ctypes.c_int64),
+        ("wide_items", ctypes.c_int64),
+        ("wide_frontier", ctypes.c_int64),
+        ("wide_ms", ctypes.c_float),
+        ("pad", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
-        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "variant_count"}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("variant_count", "pad")}
         d["variant_count"] = list(self.variant_count)
         return d
 
@@ -151,7 +157,7 @@ def default_options() -> Options:
 
 
 def make_options(variant="auto", device_loop=True, validate=True, owner_rule=0, compact=True,
-                 steps_per_sync=0, mlp_weights=None) -> Options:
+                 steps_per_sync=0, mlp_weights=None, profile=False) -> Options:
     o = default_options()
     o.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
     o.device_loop = int(bool(device_loop))
@@ -160,6 +166,7 @@ def make_options(variant="auto", device_loop=True, validate=True, owner_rule=0, 
     o.compact = int(bool(compact))
     o.steps_per_sync = int(steps_per_sync)
     o.mlp_weights = None if mlp_weights is None else ctypes.c_void_p(mlp_weights.data_ptr())
+    o.profile = int(bool(profile))
     return o
 
 
@@ -226,7 +233,7 @@ class Workspace:
 
 def truss_decompose(offsets, adj, *, variant="auto", device_loop=True, validate=True, owner_rule=0,
                     compact=True, steps_per_sync=0, mlp_weights=None, stream=None, workspace=None,
-                    out=None, return_stats=False, trace_capacity=0):
+                    out=None, return_stats=False, trace_capacity=0, profile=False):
     """Trussness (int32, >= 2) of every edge of a simple undirected CSR graph, on the GPU.
 
     offsets: int64 (or int32) [n+1]; adj: int32 [2m]; numpy arrays (copied to the GPU) or
@@ -242,7 +249,7 @@ def truss_decompose(offsets, adj, *, variant="auto", device_loop=True, validate=
     n = off_t.numel() - 1
     two_m = adj_t.numel()
     m = two_m // 2
-    opt = make_options(variant, device_loop, validate, owner_rule, compact, steps_per_sync, mlp_weights)
+    opt = make_options(variant, device_loop, validate, owner_rule, compact, steps_per_sync, mlp_weights, profile)
     if workspace is None:
         nb = workspace_bytes(n, two_m, opt) + (8 * (n + 1) + 256 if off32 else 0)
         _buf, wptr = alloc_workspace(nb)

@@ -7,10 +7,11 @@
 #define SMALL_THREADS 512    // threads per block of the fused launch
 #define SMALL_BLOCKS 256     // blocks of the fused launch
 #define ALONE_FRONTIER 512   // the fused launch's last block goes on alone on frontiers up to this size,
-#define ALONE_ITEMS 4096     // with at most this many intersection items,
+#define ALONE_ITEMS 2048     // with at most this many intersection items,
 #define ALONE_ALIVE 32768    // and scans alone when the alive list is at most this long
 #define GALLOP_K 8           // short-row entries per item when galloping
 #define GALLOP_RATIO 32      // AUTO gallops when the longer row is at most this many times the shorter
+#define GALLOP_MIN 128       // and the shorter row has at least this many entries
 
 // Everything a peeling kernel touches.
 struct PeelArgs {

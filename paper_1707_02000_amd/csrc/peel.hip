@@ -16,6 +16,8 @@
 #include <limits.h>
 #include <string.h>
 
+#include <vector>
+
 #include "peel.h"
 #include "scan.h"
 
@@ -66,7 +68,9 @@ __device__ __forceinline__ Rows rows_of(const Csr& c, int2 uv) {
 __device__ __forceinline__ i64 chunk_of(int variant, i64 slen, i64 llen) {
   if (variant == TRUSS_VARIANT_BSEARCH) return 1;
   if (variant == TRUSS_VARIANT_MERGE) return GALLOP_K;
-  return (llen <= GALLOP_RATIO * slen) ? GALLOP_K : 1;  // AUTO: per edge, by row-length ratio
+  // AUTO: one entry per item everywhere -- the sub-levels are latency-bound, and
+  // the most independent searches in flight beats the fewer probes of galloping
+  return 1;
 }
 
 // Work of a frontier edge at level l (items): the shorter working row in chunks;
@@ -427,6 +431,11 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_psl_bsearch(WideLen f, const i64*
   const i64 total = P[npairs];
   const i32 l = ctl->level;
   const int variant = ctl->variant;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {  // accounting for the roofline report
+    atomicAdd((unsigned long long*)&ctl->wide_items, (unsigned long long)total);
+    atomicAdd((unsigned long long*)&ctl->wide_frontier, (unsigned long long)npairs);
+    atomicAdd(&ctl->wide_launches, 1);
+  }
   const i32* curr = ctl->sel ? a.F1 : a.F0;
   i32* next = ctl->sel ? a.F0 : a.F1;
   const Csr c = a.csr.pick(ctl->csel);
@@ -533,7 +542,36 @@ PeelArgs peel_args(const Work& w, const truss_options& opt) {
 }
 
 // One launch sequence for the current loop state (the state was read into hc).
-static truss_status launch_round(const Work& w, const PeelArgs& a, const Ctl& hc, hipStream_t s, int* kind) {
+// Device time of every launch of the wide sub-level kernel (event pairs).
+struct KernelClock {
+  std::vector<hipEvent_t> ev;
+  size_t used = 0;
+  hipError_t begin(hipStream_t s) { return mark(s); }
+  hipError_t end(hipStream_t s) { return mark(s); }
+  hipError_t mark(hipStream_t s) {
+    if (used == ev.size()) {
+      hipEvent_t e;
+      hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return r;
+      ev.push_back(e);
+    }
+    return hipEventRecord(ev[used++], s);
+  }
+  float total_ms() {
+    float t = 0.f;
+    for (size_t i = 0; i + 1 < used; i += 2) {
+      float x = 0.f;
+      if (hipEventElapsedTime(&x, ev[i], ev[i + 1]) == hipSuccess) t += x;
+    }
+    return t;
+  }
+  ~KernelClock() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+};
+
+static truss_status launch_round(const Work& w, const PeelArgs& a, const Ctl& hc, hipStream_t s, int* kind,
+                                 KernelClock* prof) {
   if (hc.ncurr == 0) {
     *kind = 0;
     hipLaunchKernelGGL(k_scan_level, dim3(grid_for(((i64)hc.nalive + SCAN_ITEMS - 1) / SCAN_ITEMS, 2048)),
@@ -543,9 +581,13 @@ static truss_status launch_round(const Work& w, const PeelArgs& a, const Ctl& hc
     hipLaunchKernelGGL(k_psl_small, dim3(SMALL_BLOCKS), dim3(SMALL_THREADS), 0, s, a);
   } else {
     *kind = 2;
-    WideLen f{a};
-    PKT_HIP(scan_launch(f, w.partial, w.X, s));
-    hipLaunchKernelGGL(k_psl_bsearch, dim3(2048), dim3(PKT_BLOCK), 0, s, f, (const i64*)w.X);
+    if (hc.level > 0) {  // level 0: frontier edges lie in no triangle, nothing to intersect
+      WideLen f{a};
+      PKT_HIP(scan_launch(f, w.partial, w.X, s));
+      if (prof) PKT_HIP(prof->begin(s));
+      hipLaunchKernelGGL(k_psl_bsearch, dim3(2048), dim3(PKT_BLOCK), 0, s, f, (const i64*)w.X);
+      if (prof) PKT_HIP(prof->end(s));
+    }
     hipLaunchKernelGGL(k_finalize, dim3(grid_for(hc.ncurr, 1024)), dim3(PKT_BLOCK), 0, s, a);
   }
   PKT_LAUNCH_CHECK();
@@ -595,6 +637,7 @@ truss_status run_single(const Work& w, const truss_options& opt, truss_stats* st
     PKT_HIP(hipEventCreate(&tev[0]));
     PKT_HIP(hipEventCreate(&tev[1]));
   }
+  KernelClock clock;
   Ctl hc;
   st = read_ctl(w, &hc, s);
   if (st) return st;
@@ -614,7 +657,7 @@ truss_status run_single(const Work& w, const truss_options& opt, truss_stats* st
     const Ctl before = hc;
     int kind = 0;
     if (trace) PKT_HIP(hipEventRecord(tev[0], s));
-    st = launch_round(w, a, hc, s, &kind);
+    st = launch_round(w, a, hc, s, &kind, opt.profile ? &clock : nullptr);
     if (st) return st;
     if (trace) PKT_HIP(hipEventRecord(tev[1], s));
     st = read_ctl(w, &hc, s);
@@ -628,7 +671,8 @@ truss_status run_single(const Work& w, const truss_options& opt, truss_stats* st
       r.rounds = hc.sublevels - before.sublevels;
       r.frontier = before.ncurr;
       r.items = -1;
-      if (kind == 2) PKT_HIP(hipMemcpy(&r.items, w.X + before.ncurr, sizeof(i64), hipMemcpyDeviceToHost));
+      if (kind == 2 && before.level > 0)
+        PKT_HIP(hipMemcpy(&r.items, w.X + before.ncurr, sizeof(i64), hipMemcpyDeviceToHost));
       PKT_HIP(hipEventElapsedTime(&r.ms, tev[0], tev[1]));
     }
   }
@@ -660,6 +704,10 @@ truss_status run_single(const Work& w, const truss_options& opt, truss_stats* st
     stats->ms_peel = tm.ms(3, 4);
     stats->ms_total = tm.ms(0, 5);
     stats->variant_count[hc.variant] = hc.sublevels;
+    stats->wide_launches = hc.wide_launches;
+    stats->wide_items = hc.wide_items;
+    stats->wide_frontier = hc.wide_frontier;
+    stats->wide_ms = opt.profile ? clock.total_ms() : 0.f;
   }
   return TRUSS_OK;
 }

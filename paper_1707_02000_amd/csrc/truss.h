@@ -29,7 +29,10 @@ struct Ctl {
   i64 items;       // intersection items of the current sub-level (filled by the scan of P)
   i64 tri3;        // sum of initial supports (= 3 x triangles)
   i32 work_queue;  // next vertex for the support kernel's work queue
-  i32 pad[10];
+  i32 wide_launches;  // launches of the wide sub-level kernel that found work
+  i64 wide_items;     // their intersection items
+  i64 wide_frontier;  // their frontier edges
+  i32 pad[5];
 };
 
 // Adjacency with edge ids: rows off[u]..off[u+1] of adj (sorted) and eid.

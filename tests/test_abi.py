@@ -63,7 +63,8 @@ def test_default_options_and_struct_sizes(lib):
     o = pkt.default_options()
     assert (o.variant, o.device_loop, o.validate, o.owner_rule, o.compact) == (0, 1, 1, 0, 1)
     assert ctypes.sizeof(pkt.Options) == 64
-    assert ctypes.sizeof(pkt.Stats) == 104
+    assert ctypes.sizeof(pkt.Stats) == 136
+    assert ctypes.sizeof(pkt.TraceRecord) == 72
 
 
 def test_workspace_bytes_host_only(lib):
