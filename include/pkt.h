@@ -103,7 +103,10 @@ typedef struct {
   truss_trace* trace;        /* host: per-sequence trace of the peeling loop, or NULL */
   int32_t profile;           /* 1 = time every launch of the wide sub-level kernel with events
                                 (truss_stats.wide_ms) */
-  int32_t reserved[5];       /* must be zero */
+  int32_t batch_sequential;  /* truss_decompose_batched: 1 = one graph after another through the
+                                single-graph path (a comparison point); 0 = all graphs at once as
+                                one disjoint union (default) */
+  int32_t reserved[4];       /* must be zero */
 } truss_options;
 
 typedef struct {
@@ -173,8 +176,10 @@ truss_status truss_edge_list(int32_t n, const int64_t* offsets, const int32_t* a
                              int32_t* el_v, void* workspace, size_t workspace_bytes, void* stream);
 
 /*
- * Batched decomposition of many independent small graphs in one persistent
- * launch (each workgroup takes whole graphs from a queue, largest first).
+ * Batched decomposition of many independent graphs.  By default they are
+ * decomposed together as one disjoint union (one level loop and one launch
+ * sequence for the whole batch; trussness is per connected component and the
+ * union's edge order is the packed order below).
  *   num_graphs       G >= 0
  *   graph_vtx_off    device, int64[G+1]: the offsets of graph g occupy
  *                    offsets_packed[graph_vtx_off[g] .. graph_vtx_off[g+1]), i.e.

@@ -48,7 +48,8 @@ class Options(ctypes.Structure):
         ("mlp_weights", ctypes.c_void_p),
         ("trace", ctypes.c_void_p),
         ("profile", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 5),
+        ("batch_sequential", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 4),
     ]
 
 
@@ -307,7 +308,7 @@ def edge_list(offsets, adj, *, stream=None):
 
 
 def truss_decompose_batched(vtx_off, adj_off, offsets_packed, adj_packed, *, variant="auto", validate=True,
-                            stream=None, workspace=None, out=None, return_stats=False):
+                            sequential=False, stream=None, workspace=None, out=None, return_stats=False):
     """Trussness of many packed graphs (layout of include/pkt.h); int32 [sum m_g] CUDA tensor."""
     torch = _torch()
     lib = load()
@@ -318,6 +319,7 @@ def truss_decompose_batched(vtx_off, adj_off, offsets_packed, adj_packed, *, var
     G = vo.numel() - 1
     total_vtx, total_adj = int(op.numel()), int(ap.numel())
     opt = make_options(variant, True, validate)
+    opt.batch_sequential = int(bool(sequential))
     if workspace is None:
         nb = ctypes.c_size_t(0)
         _check(lib.truss_batched_workspace_bytes(G, total_vtx, total_adj, ctypes.byref(opt), ctypes.byref(nb)))

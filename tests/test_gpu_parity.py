@@ -132,11 +132,38 @@ def test_malformed_inputs_rejected(gpu_lib):
     assert ei.value.name in ("TRUSS_E_ARG", "TRUSS_E_RANGE")
 
 
-def test_batched_matches_oracle(gpu_lib):
+@pytest.mark.parametrize("sequential", [False, True])
+def test_batched_matches_oracle(gpu_lib, sequential):
     b = gg.batch(24, 64, 700, seed=11)
-    say("case batch24", b.total_m)
-    tau = gpu_lib.truss_decompose_batched(b.vtx_off, b.adj_off, b.offsets, b.adj).cpu().numpy()
+    say("case batch24", b.total_m, "sequential", sequential)
+    tau = gpu_lib.truss_decompose_batched(b.vtx_off, b.adj_off, b.offsets, b.adj,
+                                          sequential=sequential).cpu().numpy()
     for i in range(b.num_graphs):
+        g = b.graph(i)
+        s = int(b.adj_off[i]) // 2
+        assert np.array_equal(tau[s:s + g.m], oracle.truss(g)), i
+
+
+def test_batched_edge_cases(gpu_lib):
+    graphs = [gg.from_edges(0, []), gg.from_edges(5, []), gg.from_edges(3, [(0, 1), (1, 2), (0, 2)]),
+              gg.from_edges(1, []), gg.rmat(9, 8, seed=2), gg.from_edges(4, itertools.combinations(range(4), 2))]
+    b = gg.pack(graphs)
+    tau = gpu_lib.truss_decompose_batched(b.vtx_off, b.adj_off, b.offsets, b.adj).cpu().numpy()
+    want = np.concatenate([oracle.truss(g) for g in graphs])
+    assert np.array_equal(tau, want)
+    bad = gg.pack([gg.from_edges(3, [(0, 1)]), gg.from_edges(2, [(0, 1)])])
+    bad.adj[0] = 5  # local id beyond its graph
+    with pytest.raises(gpu_lib.TrussError) as ei:
+        gpu_lib.truss_decompose_batched(bad.vtx_off, bad.adj_off, bad.offsets, bad.adj)
+    assert ei.value.name in ("TRUSS_E_RANGE", "TRUSS_E_NOT_SYMMETRIC", "TRUSS_E_NOT_SIMPLE")
+
+
+def test_batched_full_config_sample(gpu_lib):
+    # the 4096-graph recipe at its full size range, every 64th graph checked against the oracle
+    b = gg.batch(256, 64, 16384, seed=1)
+    say("case batch256", b.total_m)
+    tau = gpu_lib.truss_decompose_batched(b.vtx_off, b.adj_off, b.offsets, b.adj, validate=False).cpu().numpy()
+    for i in range(0, b.num_graphs, 64):
         g = b.graph(i)
         s = int(b.adj_off[i]) // 2
         assert np.array_equal(tau[s:s + g.m], oracle.truss(g)), i
