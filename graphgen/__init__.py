@@ -100,6 +100,19 @@ class Batch:
     def total_m(self) -> int:
         return int(self.adj_off[-1]) // 2
 
+    def union(self) -> Graph:
+        """The disjoint union as one graph (vertex ids shifted by each graph's vertex base)."""
+        G = self.num_graphs
+        n_g = np.diff(self.vtx_off) - 1
+        vbase = np.concatenate([[0], np.cumsum(n_g)]).astype(np.int64)
+        off = np.empty(int(vbase[-1]) + 1, np.int64)
+        for g in range(G):
+            a = int(self.vtx_off[g])
+            off[vbase[g]:vbase[g + 1]] = self.offsets[a:a + n_g[g]].astype(np.int64) + self.adj_off[g]
+        off[-1] = self.adj_off[-1]
+        shift = np.repeat(vbase[:-1], np.diff(self.adj_off))
+        return Graph(int(vbase[-1]), off, (self.adj.astype(np.int64) + shift).astype(np.int32), name="batch-union")
+
     def graph(self, g: int) -> Graph:
         a, b = int(self.vtx_off[g]), int(self.vtx_off[g + 1])
         s, t = int(self.adj_off[g]), int(self.adj_off[g + 1])

@@ -57,27 +57,47 @@ typedef enum {
   TRUSS_E_INTERNAL = 7       /* iteration bound exceeded (a level or sub-level watchdog) */
 } truss_status;
 
-/* Intersection kernel used by the peeling sub-levels.  Every choice gives the
- * same trussness; only the running time differs. */
+/* How each frontier round (sub-level) of the peeling is launched.  Every choice
+ * gives the same trussness; only the running time differs. */
 typedef enum {
-  TRUSS_VARIANT_AUTO = 0,    /* built-in heuristic per sub-level */
-  TRUSS_VARIANT_BSEARCH = 1, /* one lane per entry of the shorter row, binary search in the longer */
-  TRUSS_VARIANT_MERGE = 2,   /* one wave per frontier edge, merge of the two rows */
-  TRUSS_VARIANT_LDS = 3,     /* longer row staged in LDS, shorter row probed there */
-  TRUSS_VARIANT_LEARNED = 4  /* MLP cost model (truss_options.mlp_weights) picks per sub-level */
+  TRUSS_CHOICE_FUSED = 0,        /* one launch, 256 blocks: work prefix in LDS, items, finalize
+                                    (frontiers of at most 2048 edges) */
+  TRUSS_CHOICE_FUSED_NARROW = 1, /* the same with 32 blocks */
+  TRUSS_CHOICE_WIDE = 2,         /* device scan of per-edge work, then 2048 blocks of items
+                                    (one binary search per shorter-row entry), then finalize */
+  TRUSS_CHOICE_WIDE_NARROW = 3,  /* the same with 256 blocks */
+  TRUSS_CHOICE_WIDE_GALLOP = 4,  /* wide, 8 shorter-row entries per item, galloping search */
+  TRUSS_NUM_CHOICES = 5
+} truss_choice;
+
+/* Policy that picks the launch of every round. */
+typedef enum {
+  TRUSS_VARIANT_AUTO = 0,    /* built-in heuristic: FUSED up to 2048 frontier edges, else WIDE */
+  TRUSS_VARIANT_BSEARCH = 1, /* same as AUTO (binary search everywhere) */
+  TRUSS_VARIANT_MERGE = 2,   /* galloping search in every round (FUSED rounds gallop too) */
+  TRUSS_VARIANT_FIXED = 3,   /* every round uses truss_options.force_choice (where valid) */
+  TRUSS_VARIANT_LEARNED = 4  /* the MLP cost model (truss_options.mlp_weights) predicts the time
+                                of every valid choice from the frontier's features and the
+                                cheapest is launched; the heuristic is its fallback */
 } truss_variant;
+
+/* Features of a frontier, in the order the cost model and the trace use them:
+ * log2(1 + frontier edges), log2(1 + mean endpoint degree), log2(1 + max endpoint
+ * degree), log2(1 + p99 endpoint degree) (from a log2 histogram), log2(1 + level),
+ * log2(1 + mean shorter-row length).  Degrees are of the working adjacency. */
+#define TRUSS_NUM_FEATURES 6
 
 /* One record per launch sequence of the peeling loop (when tracing). */
 typedef struct {
   int32_t level;             /* support level at the start */
-  int32_t kind;              /* 0 level scan, 1 fused small-frontier launch, 2 wide frontier */
-  int32_t variant;           /* truss_variant used for kinds 1 and 2 */
+  int32_t kind;              /* 0 level scan, 1 fused launch, 2 wide launch sequence */
+  int32_t choice;            /* truss_choice launched (kinds 1 and 2) */
   int32_t rounds;            /* frontier rounds completed by the sequence */
   int64_t frontier;          /* frontier size at the start */
   int64_t items;             /* intersection items of the first round (kind 2), else -1 */
   float ms;                  /* device time of the sequence */
-  float features[8];         /* cost-model features at the start (truss_features order) */
-  int32_t pad;
+  float features[8];         /* the frontier's features (first TRUSS_NUM_FEATURES used) */
+  int32_t round_index;       /* index of the sequence's first frontier round in the run */
 } truss_trace_record;
 
 /* Host-side trace buffer: the library appends up to `capacity` records and
@@ -106,7 +126,11 @@ typedef struct {
   int32_t batch_sequential;  /* truss_decompose_batched: 1 = one graph after another through the
                                 single-graph path (a comparison point); 0 = all graphs at once as
                                 one disjoint union (default) */
-  int32_t reserved[4];       /* must be zero */
+  int32_t force_choice;      /* truss_choice for TRUSS_VARIANT_FIXED */
+  int32_t single_round;      /* 1 = every launch sequence runs exactly one frontier round (no
+                                continuation of tiny rounds inside the fused launch); for
+                                collecting per-round timing traces */
+  int32_t reserved[2];       /* must be zero */
 } truss_options;
 
 typedef struct {
@@ -121,7 +145,7 @@ typedef struct {
   float ms_support;
   float ms_peel;         /* level loop: scans, sub-levels, compactions */
   float ms_total;
-  int64_t variant_count[5]; /* sub-levels run with each truss_variant */
+  int64_t choice_count[5];  /* launch sequences run with each truss_choice */
   /* the wide sub-level intersection kernel (the dominant kernel) */
   int64_t wide_launches;   /* launches that found work */
   int64_t wide_items;      /* intersection items (one per shorter-row entry searched) */
@@ -201,6 +225,48 @@ truss_status truss_decompose_batched(int32_t num_graphs, const int64_t* graph_vt
                                      int64_t total_vtx_entries, int64_t total_adj, void* workspace,
                                      size_t workspace_bytes, const truss_options* opt, truss_stats* stats,
                                      void* stream);
+
+/*
+ * The launch cost model of TRUSS_VARIANT_LEARNED: an fp32 MLP from the
+ * TRUSS_NUM_FEATURES frontier features to one predicted log2(device microseconds)
+ * per truss_choice (3 hidden layers of 64, ReLU).  Weights are
+ * truss_mlp_num_params() floats in device memory: feature mean and standard
+ * deviation (for normalisation), then each layer's weights and biases.  Rows of X
+ * are feature vectors, rows of T the measured log2 times, rows of M 1 where a
+ * choice was measured (0 otherwise); all device, row-major.  Training minimises
+ * the masked mean squared error.  The tuning workflow and its traces are in
+ * paper_1707_02000_amd/tuner.py; this is not part of the decomposition itself.
+ */
+int32_t truss_mlp_num_params(void);
+
+/* Device bytes of workspace for n rows (forward, gradient, training). */
+size_t truss_mlp_workspace_bytes(int32_t n);
+
+/* Normalisation from X, layers seeded uniform in +-1/sqrt(fan_in), output biases
+ * the mean measured target per choice. */
+truss_status truss_mlp_init(const float* X, const float* T, const float* M, int32_t n, uint64_t seed,
+                            float* weights, void* stream);
+
+/* Y[n][TRUSS_NUM_CHOICES] = model(X[n][TRUSS_NUM_FEATURES]). */
+truss_status truss_mlp_forward(const float* X, int32_t n, const float* weights, float* Y, void* workspace,
+                               size_t workspace_bytes, void* stream);
+
+/* Gradient (truss_mlp_num_params floats; zero for the normalisation entries) and
+ * loss (one float) of the masked mean squared error, all device. */
+truss_status truss_mlp_gradient(const float* X, const float* T, const float* M, int32_t n, const float* weights,
+                                float* grad, float* loss, void* workspace, size_t workspace_bytes, void* stream);
+
+/* `steps` full-batch Adam steps (beta 0.9 / 0.999, eps 1e-8) at rate lr, in place;
+ * loss_history (device, `steps` floats, or NULL) receives the loss before each step. */
+truss_status truss_mlp_train(const float* X, const float* T, const float* M, int32_t n, float* weights, int32_t steps,
+                             float lr, float* loss_history, void* workspace, size_t workspace_bytes, void* stream);
+
+/* The peeling loop's decision for n frontiers: choice[i] = the valid choice of
+ * least predicted time (fused choices are valid up to 2048 frontier edges, ncurr
+ * gives each frontier's size); Y (or NULL) receives the predictions.  Uses the same
+ * device inference routine as the loop. */
+truss_status truss_mlp_choose(const float* X, const int32_t* ncurr, int32_t n, const float* weights, int32_t* choice,
+                              float* Y, void* stream);
 
 /* Static message for a status code. */
 const char* truss_strerror(truss_status status);

@@ -22,7 +22,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpkt.so")
 
-VARIANTS = {"auto": 0, "bsearch": 1, "merge": 2, "lds": 3, "learned": 4}
+VARIANTS = {"auto": 0, "bsearch": 1, "merge": 2, "fixed": 3, "learned": 4}
+CHOICES = ["fused", "fused_narrow", "wide", "wide_narrow", "wide_gallop"]
+NUM_FEATURES = 6
 
 STATUS = {
     0: "TRUSS_OK", 1: "TRUSS_E_ARG", 2: "TRUSS_E_NOT_SIMPLE", 3: "TRUSS_E_NOT_SYMMETRIC",
@@ -49,7 +51,9 @@ class Options(ctypes.Structure):
         ("trace", ctypes.c_void_p),
         ("profile", ctypes.c_int32),
         ("batch_sequential", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 4),
+        ("force_choice", ctypes.c_int32),
+        ("single_round", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 
@@ -66,7 +70,7 @@ class Stats(ctypes.Structure):
         ("ms_support", ctypes.c_float),
         ("ms_peel", ctypes.c_float),
         ("ms_total", ctypes.c_float),
-        ("variant_count", ctypes.c_int64 * 5),
+        ("choice_count", ctypes.c_int64 * 5),
         ("wide_launches", ctypes.c_int64),
         ("wide_items", ctypes.c_int64),
         ("wide_frontier", ctypes.c_int64),
@@ -75,8 +79,8 @@ class Stats(ctypes.Structure):
     ]
 
     def as_dict(self) -> dict:
-        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("variant_count", "pad")}
-        d["variant_count"] = list(self.variant_count)
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("choice_count", "pad")}
+        d["choice_count"] = list(self.choice_count)
         return d
 
 
@@ -84,17 +88,17 @@ class TraceRecord(ctypes.Structure):
     _fields_ = [
         ("level", ctypes.c_int32),
         ("kind", ctypes.c_int32),
-        ("variant", ctypes.c_int32),
+        ("choice", ctypes.c_int32),
         ("rounds", ctypes.c_int32),
         ("frontier", ctypes.c_int64),
         ("items", ctypes.c_int64),
         ("ms", ctypes.c_float),
         ("features", ctypes.c_float * 8),
-        ("pad", ctypes.c_int32),
+        ("round_index", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
-        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("features", "pad")}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "features"}
         d["features"] = list(self.features)
         return d
 
@@ -123,6 +127,18 @@ _SIGS = {
     "truss_decompose_batched": (ctypes.c_int, [ctypes.c_int32] + [ctypes.c_void_p] * 5
                                 + [ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t]
                                 + [ctypes.c_void_p] * 3),
+    "truss_mlp_num_params": (ctypes.c_int32, []),
+    "truss_mlp_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32]),
+    "truss_mlp_init": (ctypes.c_int, [ctypes.c_void_p] * 3 + [ctypes.c_int32, ctypes.c_uint64, ctypes.c_void_p,
+                                                              ctypes.c_void_p]),
+    "truss_mlp_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "truss_mlp_gradient": (ctypes.c_int, [ctypes.c_void_p] * 3 + [ctypes.c_int32] + [ctypes.c_void_p] * 4
+                           + [ctypes.c_size_t, ctypes.c_void_p]),
+    "truss_mlp_train": (ctypes.c_int, [ctypes.c_void_p] * 3 + [ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
+                                                              ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p,
+                                                              ctypes.c_size_t, ctypes.c_void_p]),
+    "truss_mlp_choose": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32] + [ctypes.c_void_p] * 4),
     "truss_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "truss_last_error": (ctypes.c_char_p, []),
 }
@@ -158,7 +174,8 @@ def default_options() -> Options:
 
 
 def make_options(variant="auto", device_loop=True, validate=True, owner_rule=0, compact=True,
-                 steps_per_sync=0, mlp_weights=None, profile=False) -> Options:
+                 steps_per_sync=0, mlp_weights=None, profile=False, force_choice=None,
+                 single_round=False) -> Options:
     o = default_options()
     o.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
     o.device_loop = int(bool(device_loop))
@@ -168,6 +185,10 @@ def make_options(variant="auto", device_loop=True, validate=True, owner_rule=0, 
     o.steps_per_sync = int(steps_per_sync)
     o.mlp_weights = None if mlp_weights is None else ctypes.c_void_p(mlp_weights.data_ptr())
     o.profile = int(bool(profile))
+    if force_choice is not None:
+        o.variant = VARIANTS["fixed"]
+        o.force_choice = CHOICES.index(force_choice) if isinstance(force_choice, str) else int(force_choice)
+    o.single_round = int(bool(single_round))
     return o
 
 
@@ -234,7 +255,8 @@ class Workspace:
 
 def truss_decompose(offsets, adj, *, variant="auto", device_loop=True, validate=True, owner_rule=0,
                     compact=True, steps_per_sync=0, mlp_weights=None, stream=None, workspace=None,
-                    out=None, return_stats=False, trace_capacity=0, profile=False):
+                    out=None, return_stats=False, trace_capacity=0, profile=False, force_choice=None,
+                    single_round=False):
     """Trussness (int32, >= 2) of every edge of a simple undirected CSR graph, on the GPU.
 
     offsets: int64 (or int32) [n+1]; adj: int32 [2m]; numpy arrays (copied to the GPU) or
@@ -250,7 +272,8 @@ def truss_decompose(offsets, adj, *, variant="auto", device_loop=True, validate=
     n = off_t.numel() - 1
     two_m = adj_t.numel()
     m = two_m // 2
-    opt = make_options(variant, device_loop, validate, owner_rule, compact, steps_per_sync, mlp_weights, profile)
+    opt = make_options(variant, device_loop, validate, owner_rule, compact, steps_per_sync, mlp_weights, profile,
+                       force_choice, single_round)
     if workspace is None:
         nb = workspace_bytes(n, two_m, opt) + (8 * (n + 1) + 256 if off32 else 0)
         _buf, wptr = alloc_workspace(nb)

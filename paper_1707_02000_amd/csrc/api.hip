@@ -38,7 +38,11 @@ static truss_status check_options(const truss_options* o) {
     set_error("steps_per_sync must be >= 0");
     return TRUSS_E_ARG;
   }
-  for (int i = 0; i < 4; ++i)
+  if (o->variant == TRUSS_VARIANT_FIXED && (o->force_choice < 0 || o->force_choice >= TRUSS_NUM_CHOICES)) {
+    set_error("force_choice must be a truss_choice");
+    return TRUSS_E_ARG;
+  }
+  for (int i = 0; i < 2; ++i)
     if (o->reserved[i] != 0) {
       set_error("reserved option fields must be zero");
       return TRUSS_E_ARG;
@@ -127,6 +131,8 @@ void truss_default_options(truss_options* opt) {
   opt->trace = nullptr;
   opt->profile = 0;
   opt->batch_sequential = 0;
+  opt->force_choice = 0;
+  opt->single_round = 0;
 }
 
 truss_status truss_workspace_bytes(int32_t n, int64_t two_m, const truss_options* opt, size_t* bytes) {

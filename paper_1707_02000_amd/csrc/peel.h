@@ -3,15 +3,16 @@
 #include "truss.h"
 
 #define SCAN_ITEMS 16        // alive-list entries per thread per tile of a level scan
-#define SMALL_FRONTIER 2048  // frontiers up to this size run as one fused launch
+#define SMALL_FRONTIER 2048  // frontiers up to this size may run as one fused launch
 #define SMALL_THREADS 512    // threads per block of the fused launch
-#define SMALL_BLOCKS 256     // blocks of the fused launch
+#define FUSED_BLOCKS 256     // blocks of TRUSS_CHOICE_FUSED
+#define FUSED_NARROW_BLOCKS 32
+#define WIDE_BLOCKS 2048     // blocks of TRUSS_CHOICE_WIDE
+#define WIDE_NARROW_BLOCKS 256
 #define ALONE_FRONTIER 512   // the fused launch's last block goes on alone on frontiers up to this size,
 #define ALONE_ITEMS 2048     // with at most this many intersection items,
 #define ALONE_ALIVE 32768    // and scans alone when the alive list is at most this long
-#define GALLOP_K 8           // short-row entries per item when galloping
-#define GALLOP_RATIO 32      // AUTO gallops when the longer row is at most this many times the shorter
-#define GALLOP_MIN 128       // and the shorter row has at least this many entries
+#define GALLOP_K 8           // shorter-row entries per item when galloping
 
 // Everything a peeling kernel touches.
 struct PeelArgs {
@@ -25,6 +26,9 @@ struct PeelArgs {
   i32* S;
   u8* state;
   int owner_higher;
+  int single_round;
+  const float* mlp;  // cost-model weights (TRUSS_VARIANT_LEARNED) or NULL
+  int want_features; // compute frontier features at each decision (learned policy or tracing)
 };
 
 namespace pkt {

@@ -4,24 +4,31 @@
 // reducing concurrent array additions).
 //
 // Kernels (each reads the control block at entry and returns at once when the
-// loop state says it has nothing to do):
+// loop state or the round's launch choice says it has nothing to do):
 //   k_scan_level  level scan over the alive list, block-aggregated appends
-//   k_psl_small   a whole sub-level of a frontier of <= SMALL_FRONTIER edges in
-//                 one launch: every block builds the frontier's work prefix in
-//                 LDS and takes a share of the intersection items; the last block
-//                 to finish marks the states, swaps the frontiers, and goes on
-//                 alone through further tiny frontiers and short level scans
-//   k_psl_bsearch + k_finalize  wide sub-level after a device-wide scan of the
+//   k_psl_small   a whole round of a frontier of <= SMALL_FRONTIER edges in one
+//                 launch: every block builds the frontier's work prefix in LDS and
+//                 takes a share of the intersection items; the last block to
+//                 finish marks the states, swaps the frontiers, and goes on alone
+//                 through further tiny rounds and short level scans
+//   k_psl_bsearch + k_finalize  wide round after a device-wide scan of the
 //                 per-edge work (scan.h)
+// Whenever a kernel ends with a new frontier, its last block picks the launch
+// choice of the next round (heuristic, forced, or the MLP cost model, which
+// reads features sampled from the new frontier).
 #include <limits.h>
+#include <math.h>
 #include <string.h>
 
 #include <vector>
 
+#include "mlp.h"
 #include "peel.h"
 #include "scan.h"
 
 namespace {
+
+// ---------------------------------------------------------------- decrement rule
 
 // Decrement rule for edge x of a triangle whose other non-frontier-edge is y,
 // seen from frontier edge e1: x loses one unit if its support is above l and e1
@@ -62,16 +69,9 @@ __device__ __forceinline__ Rows rows_of(const Csr& c, int2 uv) {
   return r;
 }
 
-// Entries of the shorter row handled by one item.  One binary search places
-// the first entry in the longer row; the rest gallop forward from there (a
-// merge that skips), which pays off when the rows have similar lengths.
-__device__ __forceinline__ i64 chunk_of(int variant, i64 slen, i64 llen) {
-  if (variant == TRUSS_VARIANT_BSEARCH) return 1;
-  if (variant == TRUSS_VARIANT_MERGE) return GALLOP_K;
-  // AUTO: one entry per item everywhere -- the sub-levels are latency-bound, and
-  // the most independent searches in flight beats the fewer probes of galloping
-  return 1;
-}
+// Shorter-row entries handled by one item: 1 (binary search per entry) or
+// GALLOP_K (one binary search, then galloping forward in the longer row).
+__device__ __forceinline__ i64 chunk_of(int variant) { return variant == TRUSS_VARIANT_MERGE ? GALLOP_K : 1; }
 
 // Work of a frontier edge at level l (items): the shorter working row in chunks;
 // nothing at level 0 (a frontier edge at level l lies in at most l triangles
@@ -79,7 +79,7 @@ __device__ __forceinline__ i64 chunk_of(int variant, i64 slen, i64 llen) {
 __device__ __forceinline__ i64 work_of(const PeelArgs& a, const Csr& c, i32 e1, i32 l, int variant) {
   if (l == 0) return 0;
   const Rows r = rows_of(c, a.el[e1]);
-  const i64 k = chunk_of(variant, r.slen, r.le - r.lb);
+  const i64 k = chunk_of(variant);
   return (r.slen + k - 1) / k;
 }
 
@@ -103,38 +103,148 @@ __device__ __forceinline__ i64 gallop(const i32* __restrict__ B, i64 p, i64 le, 
   return lower_bound_dev(B, lo, hi, w);
 }
 
-// Triangle {u, v, w} seen from frontier edge e1, whose other two edges are es
-// and eo: unless one of them is processed, applies the decrement rule to both.
-__device__ __forceinline__ void psl_triangle(const PeelArgs& a, i32 e1, i32 es, i32 eo, i32 l, i32& y0, i32& y1) {
-  if (a.state[es] == ST_PROC || a.state[eo] == ST_PROC) return;
-  y0 = psl_rule(es, eo, e1, l, a.S, a.state, a.owner_higher);
-  y1 = psl_rule(eo, es, e1, l, a.S, a.state, a.owner_higher);
+// ---------------------------------------------------------------- features
+
+__device__ __forceinline__ int log2_bin(i64 d) { return 63 - __clzll((unsigned long long)(d + 1)); }
+
+#define FEAT_SAMPLE 512  // frontier edges sampled (evenly spaced) for the features
+
+__device__ __forceinline__ bool is_fused(int c) { return c == TRUSS_CHOICE_FUSED || c == TRUSS_CHOICE_FUSED_NARROW; }
+__device__ __forceinline__ bool is_wide(int c) { return !is_fused(c); }
+
+__device__ __forceinline__ int heuristic_choice(int policy, i32 ncurr) {
+  if (ncurr <= SMALL_FRONTIER) return TRUSS_CHOICE_FUSED;
+  return policy == TRUSS_VARIANT_MERGE ? TRUSS_CHOICE_WIDE_GALLOP : TRUSS_CHOICE_WIDE;
 }
 
+// Picks the launch of the round on the current frontier (ctl->ncurr > 0).
+// Features (learned policy or tracing only) come from up to FEAT_SAMPLE evenly
+// spaced frontier edges.  Called by every thread of one block (blockDim.x >=
+// MLP_H) after the control block's counts are final.
+__device__ void decide(const PeelArgs& a, float* sx, float* sy, float* ha, float* hb, int* schoice) {
+  Ctl* ctl = a.ctl;
+  __shared__ i64 s_sum_deg, s_sum_min, s_cnt;
+  __shared__ i32 s_max, s_hist[32];
+  if (a.want_features) {
+    if (threadIdx.x < 32) s_hist[threadIdx.x] = 0;
+    if (threadIdx.x == 0) {
+      s_sum_deg = s_sum_min = s_cnt = 0;
+      s_max = 0;
+    }
+    __syncthreads();
+    const i32 nc = ctl->ncurr;
+    const i32* curr = ctl->sel ? a.F1 : a.F0;
+    const Csr c = a.csr.pick(ctl->csel);
+    const i32 ns = min(nc, FEAT_SAMPLE);
+    i64 sd = 0, sm = 0, cnt = 0;
+    i32 mx = 0;
+    for (i32 k = threadIdx.x; k < ns; k += blockDim.x) {
+      const i32 e = curr[(i64)k * nc / ns];
+      const int2 uv = a.el[e];
+      const i64 du = c.off[uv.x + 1] - c.off[uv.x], dv = c.off[uv.y + 1] - c.off[uv.y];
+      sd += du + dv;
+      sm += min(du, dv);
+      cnt += 2;
+      mx = max(mx, (i32)max(du, dv));
+      atomicAdd(&s_hist[min(31, log2_bin(du))], 1);
+      atomicAdd(&s_hist[min(31, log2_bin(dv))], 1);
+    }
+    sd = wave_sum_i64(sd);
+    sm = wave_sum_i64(sm);
+    cnt = wave_sum_i64(cnt);
+    mx = wave_max_i32(mx);
+    if (lane_id() == 0) {
+      atomicAdd((unsigned long long*)&s_sum_deg, (unsigned long long)sd);
+      atomicAdd((unsigned long long*)&s_sum_min, (unsigned long long)sm);
+      atomicAdd((unsigned long long*)&s_cnt, (unsigned long long)cnt);
+      atomicMax(&s_max, mx);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const double cn = (double)max((i64)1, s_cnt);
+      i64 run = 0;
+      int p99 = 0;
+      for (int b = 0; b < 32; ++b) {
+        run += s_hist[b];
+        if ((double)run >= 0.99 * (double)s_cnt) {
+          p99 = b + 1;
+          break;
+        }
+      }
+      sx[0] = log2f(1.f + (float)nc);
+      sx[1] = log2f(1.f + (float)((double)s_sum_deg / cn));
+      sx[2] = log2f(1.f + (float)s_max);
+      sx[3] = (float)p99;  // log2(1 + p99 degree), in whole bins
+      sx[4] = log2f(1.f + (float)ctl->level);
+      sx[5] = log2f(1.f + (float)((double)s_sum_min / (cn * 0.5)));
+    }
+  } else if (threadIdx.x == 0) {
+    for (int i = 0; i < 8; ++i) sx[i] = 0.f;
+    sx[0] = log2f(1.f + (float)ctl->ncurr);
+  }
+  __syncthreads();
+  const int policy = ctl->policy;
+  if (policy == TRUSS_VARIANT_LEARNED && a.mlp && a.want_features) mlp_forward_block(a.mlp, sx, sy, ha, hb);
+  if (threadIdx.x == 0) {
+    const i32 nc = ctl->ncurr;
+    int c = heuristic_choice(policy, nc);
+    if (policy == TRUSS_VARIANT_FIXED) {
+      const int f = ctl->force_choice;
+      if (f >= 0 && f < TRUSS_NUM_CHOICES && (!is_fused(f) || nc <= SMALL_FRONTIER)) c = f;
+    } else if (policy == TRUSS_VARIANT_LEARNED && a.mlp && a.want_features) {
+      int best = -1;
+      float bv = INFINITY;
+      for (int k = 0; k < MLP_OUT; ++k) {
+        if (is_fused(k) && nc > SMALL_FRONTIER) continue;
+        if (isfinite(sy[k]) && sy[k] < bv) {
+          bv = sy[k];
+          best = k;
+        }
+      }
+      if (best >= 0) c = best;  // otherwise the heuristic stands
+    }
+    ctl->choice = c;
+    ctl->variant = (policy == TRUSS_VARIANT_MERGE || c == TRUSS_CHOICE_WIDE_GALLOP) ? TRUSS_VARIANT_MERGE
+                                                                                     : TRUSS_VARIANT_BSEARCH;
+    for (int i = 0; i < 8; ++i) ctl->feat[i] = i < TRUSS_NUM_FEATURES ? sx[i] : 0.f;
+    *schoice = c;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------- items
+
 // Item t of frontier edge e1: chunk t of the shorter row, located in the
-// longer row.  Edges that reached l come back in x0, x1 for a wave-aggregated
-// append; when one item produces more than two, the extra ones are appended at
-// once through spill_ctr.
+// longer row; for every triangle found with no processed edge, the decrement
+// rule on both other edges.  Edges that reached l come back in x0, x1 for a
+// wave-aggregated append; more than two from one item are appended at once.
 __device__ __forceinline__ void psl_item(const PeelArgs& a, const Csr& c, i32 e1, i64 t, i32 l, int variant,
                                          i32& x0, i32& x1, i32* spill_next, i32* spill_ctr) {
   const Rows r = rows_of(c, a.el[e1]);
-  const i64 k = chunk_of(variant, r.slen, r.le - r.lb);
+  const i64 k = chunk_of(variant);
   const i64 j0 = r.sb + t * k, j1 = min(r.sb + r.slen, j0 + k);
   i64 p = r.lb;
   for (i64 j = j0; j < j1; ++j) {
+    const i32 es = c.eid[j];
+    if (a.state[es] == ST_PROC) continue;
     const i32 w = c.adj[j];
     p = (j == j0) ? lower_bound_dev(c.adj, p, r.le, w) : gallop(c.adj, p, r.le, w);
     if (p == r.le) break;
     if (c.adj[p] != w) continue;
-    i32 y0 = -1, y1 = -1;
-    psl_triangle(a, e1, c.eid[j], c.eid[p], l, y0, y1);
-    if (y0 >= 0) {
-      if (x0 < 0) x0 = y0; else if (x1 < 0) x1 = y0; else spill_next[atomicAdd(spill_ctr, 1)] = y0;
-    }
-    if (y1 >= 0) {
-      if (x0 < 0) x0 = y1; else if (x1 < 0) x1 = y1; else spill_next[atomicAdd(spill_ctr, 1)] = y1;
-    }
+    const i32 eo = c.eid[p];
     ++p;
+    if (a.state[eo] == ST_PROC) continue;
+    const i32 y[2] = {psl_rule(es, eo, e1, l, a.S, a.state, a.owner_higher),
+                      psl_rule(eo, es, e1, l, a.S, a.state, a.owner_higher)};
+    for (int q = 0; q < 2; ++q) {
+      if (y[q] < 0) continue;
+      if (x0 < 0)
+        x0 = y[q];
+      else if (x1 < 0)
+        x1 = y[q];
+      else
+        spill_next[atomicAdd(spill_ctr, 1)] = y[q];
+    }
   }
 }
 
@@ -145,7 +255,9 @@ __device__ __forceinline__ void append_next(i32 x0, i32 x1, i32* next, i32* coun
   if (x1 >= 0) next[s1] = x1;
 }
 
-// Control-block update after a sub-level: frontier processed, next frontier
+// ---------------------------------------------------------------- control
+
+// Control-block update after a round: frontier processed, next frontier
 // current, buffers swapped, an empty next frontier ends the level.
 __device__ __forceinline__ void ctl_after_sublevel(Ctl* ctl, i32 nc, i32 nn, i32 sel) {
   ctl->processed += nc;
@@ -233,7 +345,7 @@ __device__ void scan_tiles(const PeelArgs& a, i32 l, i32 na, const i32* __restri
   }
 }
 
-// Marks the end of a sub-level: frontier edges processed, next ones current.
+// Marks the end of a round: frontier edges processed, next ones current.
 __device__ __forceinline__ void mark_states(const PeelArgs& a, const i32* curr, i32 nc, const i32* next, i32 nn,
                                             i64 tid, i64 stride) {
   for (i64 i = tid; i < nc; i += stride) a.state[curr[i]] = ST_PROC;
@@ -243,8 +355,8 @@ __device__ __forceinline__ void mark_states(const PeelArgs& a, const i32* curr, 
 // Exclusive prefix of the work of frontier edges [0, nc) into LDS P[0..nc]
 // (nc <= SMALL_FRONTIER); returns the total.  Every thread of the block calls it.
 template <int NT>
-__device__ i64 lds_work_prefix(const PeelArgs& a, const Csr& c, const i32* curr, i32 nc, i32 l, int variant,
-                                i64* P, i64* tmp) {
+__device__ i64 lds_work_prefix(const PeelArgs& a, const Csr& c, const i32* curr, i32 nc, i32 l, int variant, i64* P,
+                               i64* tmp) {
   constexpr int PER = SMALL_FRONTIER / NT;
   const int i0 = threadIdx.x * PER;
   i64 w[PER];
@@ -285,7 +397,7 @@ __device__ void lds_items(const PeelArgs& a, const Csr& c, const i32* curr, i32 
 
 // Snapshot of the control block shared through LDS by one block.
 struct CtlView {
-  i32 done, ncurr, level, sel, csel, nalive, asel, variant;
+  i32 done, ncurr, level, sel, csel, nalive, asel, variant, choice;
 };
 
 __device__ __forceinline__ void load_view(const Ctl* ctl, CtlView* v) {
@@ -298,11 +410,27 @@ __device__ __forceinline__ void load_view(const Ctl* ctl, CtlView* v) {
     v->nalive = ctl->nalive;
     v->asel = ctl->asel;
     v->variant = ctl->variant;
+    v->choice = ctl->choice;
   }
   __syncthreads();
 }
 
+// Last-arriving-block detection (every block calls it once, all threads).
+__device__ __forceinline__ bool arrive_last(Ctl* ctl, int* slast) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    *slast = (atomicAdd(&ctl->arrive, 1u) == gridDim.x - 1);
+  }
+  __syncthreads();
+  const bool last = *slast;
+  if (last) __threadfence();  // see every block's writes
+  return last;
+}
+
 }  // namespace
+
+// ---------------------------------------------------------------- kernels
 
 __global__ __launch_bounds__(PKT_BLOCK) void k_scan_level(PeelArgs a) {
   Ctl* ctl = a.ctl;
@@ -313,23 +441,20 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_scan_level(PeelArgs a) {
   i32* curr = ctl->sel ? a.F1 : a.F0;
   __shared__ i64 tmp[PKT_BLOCK / PKT_WAVE];
   __shared__ i32 sbase[2];
-  __shared__ int last;
+  __shared__ int last, schoice;
+  __shared__ float sx[8], sy[MLP_OUT], ha[MLP_H], hb[MLP_H];
   i32 mn = INT_MAX;
   scan_tiles<PKT_BLOCK>(a, l, na, A, Aout, curr, blockIdx.x, gridDim.x, mn, tmp, sbase);
   mn = wave_min_i32(mn);
   if (lane_id() == 0 && mn != INT_MAX) atomicMin(&ctl->min_above, mn);
-  __syncthreads();
+  if (!arrive_last(ctl, &last)) return;
   if (threadIdx.x == 0) {
-    __threadfence();
-    last = (atomicAdd(&ctl->arrive, 1u) == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (last && threadIdx.x == 0) {
-    __threadfence();
     ctl_after_scan(ctl, atomicAdd(&ctl->nfound, 0), atomicAdd(&ctl->nalive_out, 0),
                    atomicAdd(&ctl->min_above, 0), asel);
     ctl->arrive = 0;
   }
+  __syncthreads();
+  if (ctl->ncurr > 0) decide(a, sx, sy, ha, hb, &schoice);
 }
 
 __global__ __launch_bounds__(SMALL_THREADS) void k_psl_small(PeelArgs a) {
@@ -338,10 +463,11 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_psl_small(PeelArgs a) {
   __shared__ i64 tmp[SMALL_THREADS / PKT_WAVE];
   __shared__ i32 sbase[2];
   __shared__ CtlView v;
-  __shared__ int last;
+  __shared__ int last, schoice;
   __shared__ i32 s_nn;
+  __shared__ float sx[8], sy[MLP_OUT], ha[MLP_H], hb[MLP_H];
   load_view(ctl, &v);
-  if (v.done || v.ncurr == 0 || v.ncurr > SMALL_FRONTIER) return;
+  if (v.done || v.ncurr == 0 || v.ncurr > SMALL_FRONTIER || !is_fused(v.choice)) return;
   {
     const i32 nc = v.ncurr, l = v.level, sel = v.sel;
     const Csr c = a.csr.pick(v.csel);
@@ -350,14 +476,7 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_psl_small(PeelArgs a) {
     const i64 total = lds_work_prefix<SMALL_THREADS>(a, c, curr, nc, l, v.variant, P, tmp);
     lds_items<SMALL_THREADS>(a, c, curr, nc, l, v.variant, P, total, (i64)blockIdx.x * SMALL_THREADS,
                              (i64)gridDim.x * SMALL_THREADS, next);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      __threadfence();
-      last = (atomicAdd(&ctl->arrive, 1u) == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();  // see every block's supports, states and appends
+    if (!arrive_last(ctl, &last)) return;
     if (threadIdx.x == 0) s_nn = atomicAdd(&ctl->nnext, 0);
     __syncthreads();
     const i32 nn = s_nn;
@@ -369,35 +488,36 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_psl_small(PeelArgs a) {
     }
     __syncthreads();
   }
-  // The last block goes on alone while the work stays small: tiny frontiers,
-  // and level scans over a short alive list.
+  // The last block goes on alone while the work stays small: tiny rounds, and
+  // level scans over a short alive list.  On leaving with a frontier, it picks
+  // the launch of that frontier's round.
   for (int iter = 0; iter < (1 << 20); ++iter) {
     load_view(ctl, &v);
     if (v.done) break;
     const i32 l = v.level, sel = v.sel;
     i32* curr = (i32*)(sel ? a.F1 : a.F0);
     if (v.ncurr == 0) {
-      if (v.nalive > ALONE_ALIVE) break;
+      if (a.single_round || v.nalive > ALONE_ALIVE) break;
       const i32* A = v.asel ? a.A1 : a.A0;
       i32* Aout = v.asel ? a.A0 : a.A1;
       i32 mn = INT_MAX;
       scan_tiles<SMALL_THREADS>(a, l, v.nalive, A, Aout, curr, 0, 1, mn, tmp, sbase);
       mn = wave_min_i32(mn);
       if (lane_id() == 0 && mn != INT_MAX) atomicMin(&ctl->min_above, mn);
-      __syncthreads();
+      __syncthreads();  // every wave's minimum is in before thread 0 reads it
       if (threadIdx.x == 0)
         ctl_after_scan(ctl, atomicAdd(&ctl->nfound, 0), atomicAdd(&ctl->nalive_out, 0),
                        atomicAdd(&ctl->min_above, 0), v.asel);
       __syncthreads();
       continue;
     }
-    if (v.ncurr > ALONE_FRONTIER) break;
+    if (a.single_round || v.ncurr > ALONE_FRONTIER) break;
     const Csr c = a.csr.pick(v.csel);
     i32* next = (i32*)(sel ? a.F0 : a.F1);
     const i64 total = lds_work_prefix<SMALL_THREADS>(a, c, curr, v.ncurr, l, v.variant, P, tmp);
     if (total > ALONE_ITEMS) break;
     lds_items<SMALL_THREADS>(a, c, curr, v.ncurr, l, v.variant, P, total, 0, SMALL_THREADS, next);
-    __syncthreads();
+    __syncthreads();  // every wave's appends are counted before the count is read
     if (threadIdx.x == 0) s_nn = atomicAdd(&ctl->nnext, 0);
     __syncthreads();
     mark_states(a, curr, v.ncurr, next, s_nn, threadIdx.x, SMALL_THREADS);
@@ -405,14 +525,16 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_psl_small(PeelArgs a) {
     if (threadIdx.x == 0) ctl_after_sublevel(ctl, v.ncurr, s_nn, sel);
     __syncthreads();
   }
+  load_view(ctl, &v);
+  if (!v.done && v.ncurr > 0) decide(a, sx, sy, ha, hb, &schoice);
 }
 
-// Work of frontier edge i for the device-wide scan (wide frontiers).
+// Work of frontier edge i for the device-wide scan (wide rounds).
 struct WideLen {
   PeelArgs a;
   __device__ bool active() const {
     const Ctl* c = a.ctl;
-    return !c->done && c->ncurr > SMALL_FRONTIER && c->level > 0;
+    return !c->done && c->ncurr > 0 && c->level > 0 && is_wide(c->choice);
   }
   __device__ i64 count() const { return a.ctl->ncurr; }
   __device__ i64 len(i64 i) const {
@@ -431,14 +553,14 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_psl_bsearch(WideLen f, const i64*
   const i64 total = P[npairs];
   const i32 l = ctl->level;
   const int variant = ctl->variant;
+  const i32* curr = ctl->sel ? a.F1 : a.F0;
+  i32* next = ctl->sel ? a.F0 : a.F1;
+  const Csr c = a.csr.pick(ctl->csel);
   if (blockIdx.x == 0 && threadIdx.x == 0) {  // accounting for the roofline report
     atomicAdd((unsigned long long*)&ctl->wide_items, (unsigned long long)total);
     atomicAdd((unsigned long long*)&ctl->wide_frontier, (unsigned long long)npairs);
     atomicAdd(&ctl->wide_launches, 1);
   }
-  const i32* curr = ctl->sel ? a.F1 : a.F0;
-  i32* next = ctl->sel ? a.F0 : a.F1;
-  const Csr c = a.csr.pick(ctl->csel);
   for (i64 base = (i64)blockIdx.x * PKT_BLOCK; base < total; base += (i64)gridDim.x * PKT_BLOCK) {
     if (threadIdx.x == 0) sp[0] = upper_bound_dev(P, (i64)0, npairs + 1, base) - 1;
     if (threadIdx.x == PKT_WAVE)
@@ -457,26 +579,23 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_psl_bsearch(WideLen f, const i64*
 
 __global__ __launch_bounds__(PKT_BLOCK) void k_finalize(PeelArgs a) {
   Ctl* ctl = a.ctl;
-  if (ctl->done || ctl->ncurr <= SMALL_FRONTIER) return;
+  if (ctl->done || ctl->ncurr == 0 || !is_wide(ctl->choice)) return;
   const i32 nc = ctl->ncurr, nn = ctl->nnext, sel = ctl->sel;
   const i32* curr = sel ? a.F1 : a.F0;
   const i32* next = sel ? a.F0 : a.F1;
   mark_states(a, curr, nc, next, nn, (i64)blockIdx.x * PKT_BLOCK + threadIdx.x, (i64)gridDim.x * PKT_BLOCK);
-  __shared__ int last;
-  __syncthreads();
+  __shared__ int last, schoice;
+  __shared__ float sx[8], sy[MLP_OUT], ha[MLP_H], hb[MLP_H];
+  if (!arrive_last(ctl, &last)) return;
   if (threadIdx.x == 0) {
-    __threadfence();
-    last = (atomicAdd(&ctl->arrive, 1u) == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (last && threadIdx.x == 0) {
-    __threadfence();
     ctl_after_sublevel(ctl, nc, nn, sel);
     ctl->arrive = 0;
   }
+  __syncthreads();
+  if (ctl->ncurr > 0) decide(a, sx, sy, ha, hb, &schoice);
 }
 
-// ------------------------------------------------------------------ host side
+// ---------------------------------------------------------------- host side
 
 namespace pkt {
 
@@ -524,30 +643,10 @@ truss_status read_ctl(const Work& w, Ctl* out, hipStream_t s) {
   return TRUSS_OK;
 }
 
-}  // namespace
-
-PeelArgs peel_args(const Work& w, const truss_options& opt) {
-  PeelArgs a;
-  a.ctl = w.ctl;
-  a.F0 = w.F[0];
-  a.F1 = w.F[1];
-  a.A0 = w.A[0];
-  a.A1 = w.A[1];
-  a.el = w.el;
-  a.csr = csr_set(w);
-  a.S = w.S;
-  a.state = w.state;
-  a.owner_higher = opt.owner_rule == 1;
-  return a;
-}
-
-// One launch sequence for the current loop state (the state was read into hc).
-// Device time of every launch of the wide sub-level kernel (event pairs).
+// Device time of every launch of the wide round kernel (event pairs).
 struct KernelClock {
   std::vector<hipEvent_t> ev;
   size_t used = 0;
-  hipError_t begin(hipStream_t s) { return mark(s); }
-  hipError_t end(hipStream_t s) { return mark(s); }
   hipError_t mark(hipStream_t s) {
     if (used == ev.size()) {
       hipEvent_t e;
@@ -570,23 +669,47 @@ struct KernelClock {
   }
 };
 
+}  // namespace
+
+PeelArgs peel_args(const Work& w, const truss_options& opt) {
+  PeelArgs a;
+  a.ctl = w.ctl;
+  a.F0 = w.F[0];
+  a.F1 = w.F[1];
+  a.A0 = w.A[0];
+  a.A1 = w.A[1];
+  a.el = w.el;
+  a.csr = csr_set(w);
+  a.S = w.S;
+  a.state = w.state;
+  a.owner_higher = opt.owner_rule == 1;
+  a.single_round = opt.single_round != 0;
+  a.mlp = opt.mlp_weights;
+  a.want_features = (opt.variant == TRUSS_VARIANT_LEARNED) || opt.trace != nullptr;
+  return a;
+}
+
+// One launch sequence for the current loop state (read into hc): a level scan,
+// or the round of the current frontier as its launch choice says.
 static truss_status launch_round(const Work& w, const PeelArgs& a, const Ctl& hc, hipStream_t s, int* kind,
                                  KernelClock* prof) {
   if (hc.ncurr == 0) {
     *kind = 0;
     hipLaunchKernelGGL(k_scan_level, dim3(grid_for(((i64)hc.nalive + SCAN_ITEMS - 1) / SCAN_ITEMS, 2048)),
                        dim3(PKT_BLOCK), 0, s, a);
-  } else if (hc.ncurr <= SMALL_FRONTIER) {
+  } else if (hc.choice == TRUSS_CHOICE_FUSED || hc.choice == TRUSS_CHOICE_FUSED_NARROW) {
     *kind = 1;
-    hipLaunchKernelGGL(k_psl_small, dim3(SMALL_BLOCKS), dim3(SMALL_THREADS), 0, s, a);
+    const int blocks = hc.choice == TRUSS_CHOICE_FUSED ? FUSED_BLOCKS : FUSED_NARROW_BLOCKS;
+    hipLaunchKernelGGL(k_psl_small, dim3(blocks), dim3(SMALL_THREADS), 0, s, a);
   } else {
     *kind = 2;
     if (hc.level > 0) {  // level 0: frontier edges lie in no triangle, nothing to intersect
       WideLen f{a};
       PKT_HIP(scan_launch(f, w.partial, w.X, s));
-      if (prof) PKT_HIP(prof->begin(s));
-      hipLaunchKernelGGL(k_psl_bsearch, dim3(2048), dim3(PKT_BLOCK), 0, s, f, (const i64*)w.X);
-      if (prof) PKT_HIP(prof->end(s));
+      const int blocks = hc.choice == TRUSS_CHOICE_WIDE_NARROW ? WIDE_NARROW_BLOCKS : WIDE_BLOCKS;
+      if (prof) PKT_HIP(prof->mark(s));
+      hipLaunchKernelGGL(k_psl_bsearch, dim3(blocks), dim3(PKT_BLOCK), 0, s, f, (const i64*)w.X);
+      if (prof) PKT_HIP(prof->mark(s));
     }
     hipLaunchKernelGGL(k_finalize, dim3(grid_for(hc.ncurr, 1024)), dim3(PKT_BLOCK), 0, s, a);
   }
@@ -604,8 +727,9 @@ truss_status run_single(const Work& w, const truss_options& opt, truss_stats* st
   init.min_above = INT_MAX;
   init.nalive = (i32)w.m;
   init.csr_edges = (i32)w.m;
-  init.variant = (opt.variant == TRUSS_VARIANT_BSEARCH || opt.variant == TRUSS_VARIANT_MERGE) ? opt.variant
-                                                                                          : TRUSS_VARIANT_AUTO;
+  init.policy = opt.variant;
+  init.force_choice = opt.force_choice;
+  init.variant = opt.variant == TRUSS_VARIANT_MERGE ? TRUSS_VARIANT_MERGE : TRUSS_VARIANT_BSEARCH;
   PKT_HIP(hipMemcpyAsync(w.ctl, &init, sizeof(Ctl), hipMemcpyHostToDevice, s));
   if (opt.validate) {
     truss_status st = validate_input(w, s);
@@ -638,6 +762,7 @@ truss_status run_single(const Work& w, const truss_options& opt, truss_stats* st
     PKT_HIP(hipEventCreate(&tev[1]));
   }
   KernelClock clock;
+  i64 choice_count[TRUSS_NUM_CHOICES] = {0};
   Ctl hc;
   st = read_ctl(w, &hc, s);
   if (st) return st;
@@ -662,17 +787,20 @@ truss_status run_single(const Work& w, const truss_options& opt, truss_stats* st
     if (trace) PKT_HIP(hipEventRecord(tev[1], s));
     st = read_ctl(w, &hc, s);
     if (st) return st;
+    if (kind != 0 && before.choice >= 0 && before.choice < TRUSS_NUM_CHOICES) choice_count[before.choice]++;
     if (trace && trace->count < trace->capacity) {
       truss_trace_record& r = trace->records[trace->count++];
       memset(&r, 0, sizeof(r));
       r.level = before.level;
       r.kind = kind;
-      r.variant = kind == 0 ? 0 : before.variant;
+      r.choice = kind == 0 ? -1 : before.choice;
       r.rounds = hc.sublevels - before.sublevels;
+      r.round_index = before.sublevels;
       r.frontier = before.ncurr;
       r.items = -1;
       if (kind == 2 && before.level > 0)
         PKT_HIP(hipMemcpy(&r.items, w.X + before.ncurr, sizeof(i64), hipMemcpyDeviceToHost));
+      for (int i = 0; i < 8; ++i) r.features[i] = before.feat[i];
       PKT_HIP(hipEventElapsedTime(&r.ms, tev[0], tev[1]));
     }
   }
@@ -703,7 +831,7 @@ truss_status run_single(const Work& w, const truss_options& opt, truss_stats* st
     stats->ms_support = tm.ms(2, 3);
     stats->ms_peel = tm.ms(3, 4);
     stats->ms_total = tm.ms(0, 5);
-    stats->variant_count[hc.variant] = hc.sublevels;
+    for (int k = 0; k < TRUSS_NUM_CHOICES; ++k) stats->choice_count[k] = choice_count[k];
     stats->wide_launches = hc.wide_launches;
     stats->wide_items = hc.wide_items;
     stats->wide_frontier = hc.wide_frontier;

@@ -24,15 +24,20 @@ struct Ctl {
   i32 csel;        // working CSR: 0 = input rows, 1 or 2 = compacted copies
   i32 csr_edges;   // edges present when the working CSR was built
   i32 compactions; // working-CSR rebuilds
-  i32 variant;     // intersection kernel chosen for the current sub-level
+  i32 variant;     // intersection search of the current round (TRUSS_VARIANT_BSEARCH / MERGE)
   i32 tmax_s;      // max final support (output pass)
-  i64 items;       // intersection items of the current sub-level (filled by the scan of P)
+  i64 items;       // unused
   i64 tri3;        // sum of initial supports (= 3 x triangles)
   i32 work_queue;  // next vertex for the support kernel's work queue
   i32 wide_launches;  // launches of the wide sub-level kernel that found work
   i64 wide_items;     // their intersection items
   i64 wide_frontier;  // their frontier edges
-  i32 pad[5];
+  // decision for the current frontier
+  i32 choice;         // truss_choice picked for the round
+  i32 policy;         // truss_variant policy of the run
+  i32 force_choice;   // for TRUSS_VARIANT_FIXED
+  float feat[8];      // features of the current frontier (TRUSS_NUM_FEATURES used)
+  i32 pad[1];
 };
 
 // Adjacency with edge ids: rows off[u]..off[u+1] of adj (sorted) and eid.

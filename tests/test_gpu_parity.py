@@ -88,6 +88,11 @@ def test_support_and_edge_list(gpu_lib, make):
     dict(compact=False),
     dict(variant="bsearch"),
     dict(variant="merge"),
+    dict(force_choice="fused_narrow"),
+    dict(force_choice="wide"),
+    dict(force_choice="wide_narrow"),
+    dict(force_choice="wide_gallop"),
+    dict(single_round=True),
 ])
 def test_medium_graphs(gpu_lib, make, opts):
     g = make()
