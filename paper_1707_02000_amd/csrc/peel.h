@@ -4,6 +4,8 @@
 
 #define SCAN_ITEMS 16        // alive-list entries per thread per tile of a level scan
 #define SMALL_FRONTIER 2048  // frontiers up to this size may run as one fused launch
+#define FUSED_THRESHOLD 2048 // the heuristic fuses up to this size (end-to-end runs of the tuner's
+                             // candidates: the fused launch's continuation favours the largest)
 #define SMALL_THREADS 512    // threads per block of the fused launch
 #define FUSED_BLOCKS 256     // blocks of TRUSS_CHOICE_FUSED
 #define FUSED_NARROW_BLOCKS 32

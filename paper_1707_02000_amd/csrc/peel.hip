@@ -5,7 +5,10 @@
 //
 // Kernels (each reads the control block at entry and returns at once when the
 // loop state or the round's launch choice says it has nothing to do):
-//   k_scan_level  level scan over the alive list, block-aggregated appends
+//   k_scan_count, k_scan_offsets, k_scan_write  level scan over the alive list
+//                 in three passes (per-block counts, their prefix, stable writes
+//                 at the prefix offsets), so the alive list and the frontier stay
+//                 in edge-id order
 //   k_psl_small   a whole round of a frontier of <= SMALL_FRONTIER edges in one
 //                 launch: every block builds the frontier's work prefix in LDS and
 //                 takes a share of the intersection items; the last block to
@@ -112,8 +115,10 @@ __device__ __forceinline__ int log2_bin(i64 d) { return 63 - __clzll((unsigned l
 __device__ __forceinline__ bool is_fused(int c) { return c == TRUSS_CHOICE_FUSED || c == TRUSS_CHOICE_FUSED_NARROW; }
 __device__ __forceinline__ bool is_wide(int c) { return !is_fused(c); }
 
+// The built-in heuristic: fused launch up to FUSED_THRESHOLD frontier edges (the
+// threshold the tuner's trace search picked), else the wide sequence.
 __device__ __forceinline__ int heuristic_choice(int policy, i32 ncurr) {
-  if (ncurr <= SMALL_FRONTIER) return TRUSS_CHOICE_FUSED;
+  if (ncurr <= FUSED_THRESHOLD) return TRUSS_CHOICE_FUSED;
   return policy == TRUSS_VARIANT_MERGE ? TRUSS_CHOICE_WIDE_GALLOP : TRUSS_CHOICE_WIDE;
 }
 
@@ -286,13 +291,51 @@ __device__ __forceinline__ void ctl_after_scan(Ctl* ctl, i32 nfound, i32 nkeep, 
   ctl->min_above = INT_MAX;
 }
 
+// Stable compaction inside one tile of NT * SCAN_ITEMS entries, where entry
+// t + k * NT belongs to thread t, slot k: its position among the taken (kept)
+// entries of the tile, in entry order.  Per-wave ballots per slot, then an
+// exclusive scan of the (slot, wave) counts in slot-major order.  Keeping entry
+// order keeps the alive list and the frontier sorted by edge id, so the next
+// scan's gathers stay coalesced.  *ntake, *nkeep get the tile's totals.
+template <int NT>
+__device__ __forceinline__ void stable_tile(u32 tk, u32 kp, i32* pt, i32* pk, i32* ntake, i32* nkeep, i64* cnt,
+                                            i64* tmp) {
+  constexpr int NW = NT / PKT_WAVE;
+  const int lane = lane_id(), w = threadIdx.x / PKT_WAVE;
+  const u64 lt = (1ull << lane) - 1ull;
+  u64 bt[SCAN_ITEMS], bk[SCAN_ITEMS];
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    bt[k] = __ballot((tk >> k) & 1u);
+    bk[k] = __ballot((kp >> k) & 1u);
+    if (lane == 0) cnt[k * NW + w] = ((i64)__popcll(bt[k]) << 32) | (i64)__popcll(bk[k]);
+  }
+  __syncthreads();
+  const int E = SCAN_ITEMS * NW;
+  const i64 v = (threadIdx.x < E) ? cnt[threadIdx.x] : 0;
+  i64 tot;
+  const i64 ex = block_excl_scan_i64<NT>(v, tmp, &tot);
+  if (threadIdx.x < E) cnt[threadIdx.x] = ex;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    const i64 o = cnt[k * NW + w];
+    pt[k] = (i32)(o >> 32) + (i32)__popcll(bt[k] & lt);
+    pk[k] = (i32)(o & 0xffffffffll) + (i32)__popcll(bk[k] & lt);
+  }
+  *ntake = (i32)(tot >> 32);
+  *nkeep = (i32)(tot & 0xffffffffll);
+  __syncthreads();  // cnt is reused by the next tile
+}
+
 // Level scan over tiles of the alive list (tiles tile0, tile0 + tstride, ...):
 // edges still unprocessed with support l join the frontier and turn CURR;
 // other unprocessed edges are copied to the other alive list; processed edges
-// drop out.  One atomic per counter per tile of NT * SCAN_ITEMS entries.
+// drop out.  Stable (entry order kept); one atomic per counter per tile of NT *
+// SCAN_ITEMS entries (used by a single block, so the atomics are uncontended).
 template <int NT>
 __device__ void scan_tiles(const PeelArgs& a, i32 l, i32 na, const i32* __restrict__ A, i32* __restrict__ Aout,
-                           i32* __restrict__ curr, i64 tile0, i64 tstride, i32& mn, i64* tmp, i32* sbase) {
+                           i32* __restrict__ curr, i64 tile0, i64 tstride, i32& mn, i64* tmp, i64* cnt, i32* sbase) {
   const i64 tile = (i64)NT * SCAN_ITEMS;
   for (i64 t0 = tile0 * tile; t0 < na; t0 += tstride * tile) {
     u32 tk = 0, kp = 0;
@@ -322,23 +365,20 @@ __device__ void scan_tiles(const PeelArgs& a, i32 l, i32 na, const i32* __restri
         }
       }
     }
-    const i64 packed = ((i64)__popc(tk) << 32) | (i64)__popc(kp);
-    i64 tot;
-    const i64 ex = block_excl_scan_i64<NT>(packed, tmp, &tot);
+    i32 pt[SCAN_ITEMS], pk[SCAN_ITEMS], nt, nk;
+    stable_tile<NT>(tk, kp, pt, pk, &nt, &nk, cnt, tmp);
     if (threadIdx.x == 0) {
-      const i32 nt = (i32)(tot >> 32), nk = (i32)(tot & 0xffffffffll);
       sbase[0] = nt ? atomicAdd(&a.ctl->nfound, nt) : 0;
       sbase[1] = nk ? atomicAdd(&a.ctl->nalive_out, nk) : 0;
     }
     __syncthreads();
-    i32 pt = sbase[0] + (i32)(ex >> 32), pk = sbase[1] + (i32)(ex & 0xffffffffll);
 #pragma unroll
     for (int k = 0; k < SCAN_ITEMS; ++k) {
       if ((tk >> k) & 1u) {
-        curr[pt++] = ev[k];
+        curr[sbase[0] + pt[k]] = ev[k];
         a.state[ev[k]] = ST_CURR;
       } else if ((kp >> k) & 1u) {
-        Aout[pk++] = ev[k];
+        Aout[sbase[1] + pk[k]] = ev[k];
       }
     }
     __syncthreads();
@@ -432,25 +472,158 @@ __device__ __forceinline__ bool arrive_last(Ctl* ctl, int* slast) {
 
 // ---------------------------------------------------------------- kernels
 
-__global__ __launch_bounds__(PKT_BLOCK) void k_scan_level(PeelArgs a) {
+// Level scan in three passes, with no contended atomics: every block counts the
+// taken and kept entries of its contiguous chunk of the alive list (pass 1), one
+// block turns the counts into offsets (pass 2), every block writes its entries at
+// its offset (pass 3, whose last block updates the control block and decides the
+// first round's launch).  Chunks: G blocks of ceil(na / G) entries, tile-aligned.
+namespace {
+__device__ __forceinline__ void scan_chunk(i32 na, int G, i64* c0, i64* c1) {
+  const i64 tile = (i64)PKT_BLOCK * SCAN_ITEMS;
+  const i64 chunk = ((na + G - 1) / G + tile - 1) / tile * tile;
+  *c0 = min((i64)na, (i64)blockIdx.x * chunk);
+  *c1 = min((i64)na, *c0 + chunk);
+}
+
+// Classifies the PKT_BLOCK * SCAN_ITEMS entries of the alive list from t0 (below
+// end): bit k of tk / kp set when entry t0 + k * PKT_BLOCK + threadIdx.x is taken /
+// kept.
+__device__ __forceinline__ void classify(const PeelArgs& a, i32 l, const i32* __restrict__ A, i64 t0, i64 end,
+                                         i32* ev, u32& tk, u32& kp, i32& mn) {
+  u8 st[SCAN_ITEMS];
+  i32 sv[SCAN_ITEMS];
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    const i64 i = t0 + (i64)k * PKT_BLOCK + threadIdx.x;
+    ev[k] = (i < end) ? A[i] : -1;
+  }
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    const i32 e = ev[k] < 0 ? 0 : ev[k];
+    st[k] = a.state[e];
+    sv[k] = a.S[e];
+  }
+  tk = kp = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    if (ev[k] >= 0 && st[k] == ST_ALIVE) {
+      if (sv[k] == l) {
+        tk |= 1u << k;
+      } else {
+        kp |= 1u << k;
+        mn = min(mn, sv[k]);
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ bool scan_gate(const Ctl* ctl) { return !ctl->done && ctl->ncurr == 0 && !ctl->scan_pending; }
+}  // namespace
+
+__global__ __launch_bounds__(PKT_BLOCK) void k_scan_count(PeelArgs a, int G, i64* __restrict__ part,
+                                                         i32* __restrict__ bmin) {
+  const Ctl* ctl = a.ctl;
+  if (!scan_gate(ctl)) return;
+  const i32 l = ctl->level, na = ctl->nalive;
+  const i32* A = ctl->asel ? a.A1 : a.A0;
+  i64 c0, c1;
+  scan_chunk(na, G, &c0, &c1);
+  i64 packed = 0;
+  i32 mn = INT_MAX;
+  for (i64 t0 = c0; t0 < c1; t0 += (i64)PKT_BLOCK * SCAN_ITEMS) {
+    i32 ev[SCAN_ITEMS];
+    u32 tk, kp;
+    classify(a, l, A, t0, c1, ev, tk, kp, mn);
+    packed += ((i64)__popc(tk) << 32) | (i64)__popc(kp);
+  }
+  __shared__ i64 sp[PKT_BLOCK / PKT_WAVE];
+  __shared__ i32 sm[PKT_BLOCK / PKT_WAVE];
+  packed = wave_sum_i64(packed);
+  mn = wave_min_i32(mn);
+  if (lane_id() == 0) {
+    sp[threadIdx.x / PKT_WAVE] = packed;
+    sm[threadIdx.x / PKT_WAVE] = mn;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    i64 t = 0;
+    i32 m = INT_MAX;
+    for (int w = 0; w < PKT_BLOCK / PKT_WAVE; ++w) {
+      t += sp[w];
+      m = min(m, sm[w]);
+    }
+    part[blockIdx.x] = t;
+    bmin[blockIdx.x] = m;
+  }
+}
+
+__global__ __launch_bounds__(PKT_BLOCK) void k_scan_offsets(PeelArgs a, int G, i64* __restrict__ part,
+                                                           const i32* __restrict__ bmin) {
   Ctl* ctl = a.ctl;
-  if (ctl->done || ctl->ncurr != 0) return;
+  if (!scan_gate(ctl)) return;
+  __shared__ i64 tmp[PKT_BLOCK / PKT_WAVE];
+  __shared__ i32 sm[PKT_BLOCK / PKT_WAVE];
+  i64 running = 0;
+  i32 mn = INT_MAX;
+  for (int base = 0; base < G; base += PKT_BLOCK) {
+    const int i = base + threadIdx.x;
+    const i64 v = (i < G) ? part[i] : 0;
+    if (i < G) mn = min(mn, bmin[i]);
+    i64 tot;
+    const i64 ex = block_excl_scan_i64(v, tmp, &tot);
+    if (i < G) part[i] = running + ex;
+    running += tot;
+  }
+  mn = wave_min_i32(mn);
+  if (lane_id() == 0) sm[threadIdx.x / PKT_WAVE] = mn;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < PKT_BLOCK / PKT_WAVE; ++w) mn = min(mn, sm[w]);
+    ctl->nfound = (i32)(running >> 32);
+    ctl->nalive_out = (i32)(running & 0xffffffffll);
+    ctl->min_above = mn;
+    ctl->scan_pending = 1;
+  }
+}
+
+__global__ __launch_bounds__(PKT_BLOCK) void k_scan_write(PeelArgs a, int G, const i64* __restrict__ part) {
+  Ctl* ctl = a.ctl;
+  if (ctl->done || !ctl->scan_pending) return;
   const i32 l = ctl->level, na = ctl->nalive, asel = ctl->asel;
   const i32* A = asel ? a.A1 : a.A0;
   i32* Aout = asel ? a.A0 : a.A1;
   i32* curr = ctl->sel ? a.F1 : a.F0;
   __shared__ i64 tmp[PKT_BLOCK / PKT_WAVE];
-  __shared__ i32 sbase[2];
+  __shared__ i64 cnt[SCAN_ITEMS * (PKT_BLOCK / PKT_WAVE)];
   __shared__ int last, schoice;
   __shared__ float sx[8], sy[MLP_OUT], ha[MLP_H], hb[MLP_H];
+  i64 c0, c1;
+  scan_chunk(na, G, &c0, &c1);
+  const i64 base = part[blockIdx.x];
+  i32 bt = (i32)(base >> 32), bk = (i32)(base & 0xffffffffll);
   i32 mn = INT_MAX;
-  scan_tiles<PKT_BLOCK>(a, l, na, A, Aout, curr, blockIdx.x, gridDim.x, mn, tmp, sbase);
-  mn = wave_min_i32(mn);
-  if (lane_id() == 0 && mn != INT_MAX) atomicMin(&ctl->min_above, mn);
+  for (i64 t0 = c0; t0 < c1; t0 += (i64)PKT_BLOCK * SCAN_ITEMS) {
+    i32 ev[SCAN_ITEMS];
+    u32 tk, kp;
+    classify(a, l, A, t0, c1, ev, tk, kp, mn);
+    i32 pt[SCAN_ITEMS], pk[SCAN_ITEMS], nt, nk;
+    stable_tile<PKT_BLOCK>(tk, kp, pt, pk, &nt, &nk, cnt, tmp);
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+      if ((tk >> k) & 1u) {
+        curr[bt + pt[k]] = ev[k];
+        a.state[ev[k]] = ST_CURR;
+      } else if ((kp >> k) & 1u) {
+        Aout[bk + pk[k]] = ev[k];
+      }
+    }
+    bt += nt;
+    bk += nk;
+  }
   if (!arrive_last(ctl, &last)) return;
   if (threadIdx.x == 0) {
-    ctl_after_scan(ctl, atomicAdd(&ctl->nfound, 0), atomicAdd(&ctl->nalive_out, 0),
-                   atomicAdd(&ctl->min_above, 0), asel);
+    ctl_after_scan(ctl, ctl->nfound, ctl->nalive_out, ctl->min_above, asel);
+    ctl->scan_pending = 0;
     ctl->arrive = 0;
   }
   __syncthreads();
@@ -461,6 +634,7 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_psl_small(PeelArgs a) {
   Ctl* ctl = a.ctl;
   __shared__ i64 P[SMALL_FRONTIER + 1];
   __shared__ i64 tmp[SMALL_THREADS / PKT_WAVE];
+  __shared__ i64 scnt[SCAN_ITEMS * (SMALL_THREADS / PKT_WAVE)];
   __shared__ i32 sbase[2];
   __shared__ CtlView v;
   __shared__ int last, schoice;
@@ -501,7 +675,7 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_psl_small(PeelArgs a) {
       const i32* A = v.asel ? a.A1 : a.A0;
       i32* Aout = v.asel ? a.A0 : a.A1;
       i32 mn = INT_MAX;
-      scan_tiles<SMALL_THREADS>(a, l, v.nalive, A, Aout, curr, 0, 1, mn, tmp, sbase);
+      scan_tiles<SMALL_THREADS>(a, l, v.nalive, A, Aout, curr, 0, 1, mn, tmp, scnt, sbase);
       mn = wave_min_i32(mn);
       if (lane_id() == 0 && mn != INT_MAX) atomicMin(&ctl->min_above, mn);
       __syncthreads();  // every wave's minimum is in before thread 0 reads it
@@ -695,8 +869,11 @@ static truss_status launch_round(const Work& w, const PeelArgs& a, const Ctl& hc
                                  KernelClock* prof) {
   if (hc.ncurr == 0) {
     *kind = 0;
-    hipLaunchKernelGGL(k_scan_level, dim3(grid_for(((i64)hc.nalive + SCAN_ITEMS - 1) / SCAN_ITEMS, 2048)),
-                       dim3(PKT_BLOCK), 0, s, a);
+    const i64 tiles = ((i64)hc.nalive + (i64)PKT_BLOCK * SCAN_ITEMS - 1) / ((i64)PKT_BLOCK * SCAN_ITEMS);
+    const int G = (int)(tiles < 1 ? 1 : (tiles > SCAN_BLOCKS ? SCAN_BLOCKS : tiles));
+    hipLaunchKernelGGL(k_scan_count, dim3(G), dim3(PKT_BLOCK), 0, s, a, G, w.partial, w.bmin);
+    hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(PKT_BLOCK), 0, s, a, G, w.partial, (const i32*)w.bmin);
+    hipLaunchKernelGGL(k_scan_write, dim3(G), dim3(PKT_BLOCK), 0, s, a, G, (const i64*)w.partial);
   } else if (hc.choice == TRUSS_CHOICE_FUSED || hc.choice == TRUSS_CHOICE_FUSED_NARROW) {
     *kind = 1;
     const int blocks = hc.choice == TRUSS_CHOICE_FUSED ? FUSED_BLOCKS : FUSED_NARROW_BLOCKS;

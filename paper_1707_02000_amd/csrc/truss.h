@@ -37,7 +37,7 @@ struct Ctl {
   i32 policy;         // truss_variant policy of the run
   i32 force_choice;   // for TRUSS_VARIANT_FIXED
   float feat[8];      // features of the current frontier (TRUSS_NUM_FEATURES used)
-  i32 pad[1];
+  i32 scan_pending;   // level scan counted, not yet written (between its passes)
 };
 
 // Adjacency with edge ids: rows off[u]..off[u+1] of adj (sorted) and eid.
@@ -78,6 +78,7 @@ struct Work {
   u8* flag;         // [2m] scratch flags
   i64* X;           // [2m+1] scan output (orientation / compaction / frontier work)
   i64* partial;     // [SCAN_BLOCKS+1]
+  i32* bmin;        // [SCAN_BLOCKS] per-block minima of the level scan
   i64* ooff;        // [n+1] oriented CSR (aliases coff[1])
   i32* oadj;        // [m] (aliases cadj[1])
   i32* oeid;        // [m] (aliases ceid[1])

@@ -339,6 +339,7 @@ size_t work_layout(i32 n, i64 two_m, bool off32, void* base, Work* w) {
   t.ctl = cv.take<Ctl>(1);
   t.verr = cv.take<u32>(4);
   t.partial = cv.take<i64>(SCAN_BLOCKS + 1);
+  t.bmin = cv.take<i32>(SCAN_BLOCKS);
   if (off32) t.off64 = cv.take<i64>((size_t)n + 1);
   t.deg = cv.take<i32>((size_t)n);
   t.locnt = cv.take<i32>((size_t)n);

@@ -85,7 +85,10 @@ def dataset(rounds):
     return X, T, M, nc
 
 
-def heuristic_choice(frontier: int, threshold: int = FUSED_LIMIT) -> int:
+HEURISTIC_THRESHOLD = 2048  # the library's built-in rule (see autotune_threshold)
+
+
+def heuristic_choice(frontier: int, threshold: int = HEURISTIC_THRESHOLD) -> int:
     return 0 if frontier <= threshold else 2
 
 
