@@ -80,6 +80,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat20", choices=sorted(WORKLOADS))
     ap.add_argument("--variant", default="auto")
+    ap.add_argument("--loop", default="host", choices=["host", "device", "graph"],
+                    help="level-loop driver: host reads state per launch sequence; device/graph run gated steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (5 times), to scale "
@@ -121,7 +123,7 @@ def main():
 
     # untimed: validation + parity against the stored oracle result
     tau, st0 = pkt.truss_decompose(off, adj, validate=True, variant=args.variant, workspace=ws, out=out,
-                                   return_stats=True)
+                                   return_stats=True, device_loop=args.loop)
     tau_h = tau.cpu().numpy()
     parity = None
     gold = os.path.join(ROOT, "tests", "golden", f"{args.workload}.json")
@@ -132,7 +134,7 @@ def main():
 
     def step():
         return pkt.truss_decompose(off, adj, validate=False, variant=args.variant, workspace=ws, out=out,
-                                   return_stats=True, profile=True)[1]
+                                   return_stats=True, profile=True, device_loop=args.loop)[1]
 
     for _ in range(args.warmup):
         step()
@@ -148,7 +150,7 @@ def main():
     deg = g.degrees()
     # dominant kernel: the wide sub-level intersection kernel; its launches are timed
     # with HIP events on the library's stream inside the timed steps
-    launches = sum(s["wide_launches"] for s in stats)
+    launches = sum(s["wide_timed"] for s in stats)
     dom_ms = sum(s["wide_ms"] for s in stats)
     items = sum(s["wide_items"] for s in stats)
     frontier = sum(s["wide_frontier"] for s in stats)
@@ -177,7 +179,7 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload], "n": g.n, "m": g.m,
-                   "variant": args.variant},
+                   "variant": args.variant, "loop": args.loop},
         "parity_vs_oracle": parity,
         "wedges_per_s": pkt.wedges(deg) / (ms / 1000.0),
         "t_max": st0["t_max"],

@@ -110,7 +110,10 @@ typedef struct {
 
 typedef struct {
   int32_t variant;           /* truss_variant; default AUTO */
-  int32_t device_loop;       /* 1 = device-driven sub-level loop replayed as a hipGraph (default 1) */
+  int32_t device_loop;       /* 0 = host-driven: the host reads the loop state after every launch
+                                sequence; 1 = device-driven: batches of gated steps between host
+                                checks; 2 = as 1, the steps replayed from a captured hipGraph
+                                (default 0; a trace forces 0, profile turns 2 into 1) */
   int32_t validate;          /* 1 = check the input CSR before any other work (default 1) */
   int32_t owner_rule;        /* 0 = the lower edge id owns a two-frontier-edge triangle (the
                                 paper's rule, default); 1 = the higher id (the paper's stated
@@ -150,8 +153,10 @@ typedef struct {
   int64_t wide_launches;   /* launches that found work */
   int64_t wide_items;      /* intersection items (one per shorter-row entry searched) */
   int64_t wide_frontier;   /* frontier edges */
-  float wide_ms;           /* summed device time of its launches (opt.profile only) */
-  int32_t pad;
+  float wide_ms;           /* summed device time of its timed launches (opt.profile only) */
+  int32_t wide_timed;      /* launches timed into wide_ms: with the host-driven loop those of
+                              rounds above level 0; with the device-driven loop every launch,
+                              including those that found their gate closed */
 } truss_stats;
 
 /* Fills *opt with the defaults listed above. */

@@ -24,6 +24,16 @@ LIB_PATH = os.path.join(_HERE, "libpkt.so")
 
 VARIANTS = {"auto": 0, "bsearch": 1, "merge": 2, "fixed": 3, "learned": 4}
 CHOICES = ["fused", "fused_narrow", "wide", "wide_narrow", "wide_gallop"]
+LOOP_MODES = {"host": 0, "device": 1, "graph": 2}  # truss_options.device_loop
+
+
+def loop_mode(x) -> int:
+    """truss_options.device_loop from a name, a bool (True = device-driven) or an int."""
+    if isinstance(x, str):
+        return LOOP_MODES[x]
+    if isinstance(x, bool) or x is None:
+        return 1 if x else 0
+    return int(x)
 NUM_FEATURES = 6
 
 STATUS = {
@@ -75,11 +85,11 @@ class Stats(ctypes.Structure):
         ("wide_items", ctypes.c_int64),
         ("wide_frontier", ctypes.c_int64),
         ("wide_ms", ctypes.c_float),
-        ("pad", ctypes.c_int32),
+        ("wide_timed", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
-        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("choice_count", "pad")}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("choice_count",)}
         d["choice_count"] = list(self.choice_count)
         return d
 
@@ -173,12 +183,12 @@ def default_options() -> Options:
     return o
 
 
-def make_options(variant="auto", device_loop=True, validate=True, owner_rule=0, compact=True,
+def make_options(variant="auto", device_loop="host", validate=True, owner_rule=0, compact=True,
                  steps_per_sync=0, mlp_weights=None, profile=False, force_choice=None,
                  single_round=False) -> Options:
     o = default_options()
     o.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
-    o.device_loop = int(bool(device_loop))
+    o.device_loop = loop_mode(device_loop)
     o.validate = int(bool(validate))
     o.owner_rule = int(owner_rule)
     o.compact = int(bool(compact))
@@ -253,7 +263,7 @@ class Workspace:
         return cls(n, two_m, buf, ptr, nb.value)
 
 
-def truss_decompose(offsets, adj, *, variant="auto", device_loop=True, validate=True, owner_rule=0,
+def truss_decompose(offsets, adj, *, variant="auto", device_loop="host", validate=True, owner_rule=0,
                     compact=True, steps_per_sync=0, mlp_weights=None, stream=None, workspace=None,
                     out=None, return_stats=False, trace_capacity=0, profile=False, force_choice=None,
                     single_round=False):

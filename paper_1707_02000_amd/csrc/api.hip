@@ -34,6 +34,10 @@ static truss_status check_options(const truss_options* o) {
     set_error("owner_rule must be 0 or 1");
     return TRUSS_E_ARG;
   }
+  if (o->device_loop < 0 || o->device_loop > 2) {
+    set_error("device_loop must be 0 (host), 1 (device) or 2 (device, hipGraph)");
+    return TRUSS_E_ARG;
+  }
   if (o->steps_per_sync < 0) {
     set_error("steps_per_sync must be >= 0");
     return TRUSS_E_ARG;
@@ -122,7 +126,7 @@ void truss_default_options(truss_options* opt) {
   if (!opt) return;
   memset(opt, 0, sizeof(*opt));
   opt->variant = TRUSS_VARIANT_AUTO;
-  opt->device_loop = 1;
+  opt->device_loop = 0;
   opt->validate = 1;
   opt->owner_rule = 0;
   opt->compact = 1;

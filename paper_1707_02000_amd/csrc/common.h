@@ -17,8 +17,19 @@ typedef uint8_t u8;
 #define PKT_WAVE 64
 #define PKT_BLOCK 256  // 4 waves
 
-// Edge states of the peeling (the paper's inCurr / inNext / processed, packed).
-enum : u8 { ST_ALIVE = 0, ST_CURR = 1, ST_NEXT = 2, ST_PROC = 3 };
+// Edge states of the peeling (the paper's inCurr / inNext / processed) as one
+// byte per edge: ST_ALIVE until the edge joins a frontier, then the tag of the
+// round that processes it, three tags in rotation.  During round r an edge is
+// current iff its tag is round_tag(r), joined the next frontier iff round_tag(r +
+// 1), and processed iff ST_PROC or round_tag(r - 1): round r itself turns the
+// round_tag(r - 1) edges (its previous frontier) into ST_PROC, so that tag is
+// free again when round r + 1 hands it to its next frontier.  Ending a round is
+// then a counter update, with no pass between rounds.
+enum : u8 { ST_ALIVE = 0, ST_PROC = 1 };
+__host__ __device__ __forceinline__ u8 round_tag(int r) { return (u8)(2 + (unsigned)r % 3u); }
+__host__ __device__ __forceinline__ bool is_processed(u8 st, int r) {
+  return st == ST_PROC || st == round_tag(r + 2);
+}
 
 // Validation error bits.
 enum : u32 { VERR_RANGE = 1u, VERR_NOT_SIMPLE = 2u, VERR_NOT_SYMMETRIC = 4u };

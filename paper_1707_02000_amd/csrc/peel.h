@@ -15,12 +15,13 @@
 #define ALONE_ITEMS 2048     // with at most this many intersection items,
 #define ALONE_ALIVE 32768    // and scans alone when the alive list is at most this long
 #define GALLOP_K 8           // shorter-row entries per item when galloping
+#define DECIDE_THREADS 512   // threads of the one-block kernel that picks a round's launch
+#define CHOICE_NONE (-1)     // Ctl::choice while no launch is picked for the current frontier
 
 // Everything a peeling kernel touches.
 struct PeelArgs {
   Ctl* ctl;
-  i32* F0;
-  i32* F1;
+  i32* F[3];  // frontier buffers; round buffers by Ctl::sel (cur_of, next_of, prev_of)
   i32* A0;
   i32* A1;
   const int2* el;
@@ -32,6 +33,10 @@ struct PeelArgs {
   const float* mlp;  // cost-model weights (TRUSS_VARIANT_LEARNED) or NULL
   int want_features; // compute frontier features at each decision (learned policy or tracing)
 };
+
+__device__ __forceinline__ i32* cur_of(const PeelArgs& a, int sel) { return a.F[sel]; }
+__device__ __forceinline__ i32* next_of(const PeelArgs& a, int sel) { return a.F[sel == 2 ? 0 : sel + 1]; }
+__device__ __forceinline__ i32* prev_of(const PeelArgs& a, int sel) { return a.F[sel == 0 ? 2 : sel - 1]; }
 
 namespace pkt {
 CsrSet csr_set(const Work& w);

@@ -5,20 +5,25 @@
 //
 // Kernels (each reads the control block at entry and returns at once when the
 // loop state or the round's launch choice says it has nothing to do):
-//   k_scan_count, k_scan_offsets, k_scan_write  level scan over the alive list
-//                 in three passes (per-block counts, their prefix, stable writes
-//                 at the prefix offsets), so the alive list and the frontier stay
-//                 in edge-id order
+//   k_scan_count, k_scan_write  level scan over the alive list in two passes
+//                 (per-block counts and their prefix, then stable writes at the
+//                 prefix offsets), so the alive list and the frontier stay in
+//                 edge-id order
 //   k_psl_small   a whole round of a frontier of <= SMALL_FRONTIER edges in one
 //                 launch: every block builds the frontier's work prefix in LDS and
-//                 takes a share of the intersection items; the last block to
-//                 finish marks the states, swaps the frontiers, and goes on alone
-//                 through further tiny rounds and short level scans
-//   k_psl_bsearch + k_finalize  wide round after a device-wide scan of the
-//                 per-edge work (scan.h)
-// Whenever a kernel ends with a new frontier, its last block picks the launch
-// choice of the next round (heuristic, forced, or the MLP cost model, which
-// reads features sampled from the new frontier).
+//                 takes a share of the intersection items
+//   k_psl_bsearch wide round over a device-wide scan of the per-edge work (scan.h)
+//   k_decide      one block after each of the above: goes on alone through
+//                 further tiny rounds and short level scans, then picks the launch
+//                 of the round on the frontier left (heuristic, forced, or the MLP
+//                 cost model, which reads features sampled from the frontier)
+// Edge states are round tags (three in rotation, the previous frontier turned
+// processed by the next round's own blocks), so ending a round is a counter
+// update done by the round's last block to finish.  The round kernels stay lean (their register
+// counts set the occupancy of the item loops); the rest sits in k_decide.
+// The host either reads the control block after every launch sequence, or
+// enqueues steps holding every launch, gated, and checks in batches (optionally
+// as a replayed hipGraph).
 #include <limits.h>
 #include <math.h>
 #include <string.h>
@@ -34,22 +39,24 @@ namespace {
 // ---------------------------------------------------------------- decrement rule
 
 // Decrement rule for edge x of a triangle whose other non-frontier-edge is y,
-// seen from frontier edge e1: x loses one unit if its support is above l and e1
-// owns the triangle (y is not in the frontier, or e1 has the lower id -- the
-// higher id with owner_higher).  The atomic's old value decides: l + 1 means x
-// now sits at l and joins the next frontier; <= l means the decrement overshot
-// (another thread got there first) and is undone.  Returns x if it joined the
-// next frontier, else -1.  The plain pre-read of S may be stale: while S[x] > l
-// every older value is > l too, and once S[x] <= l it stays <= l for the level,
-// so a stale read can only cause a decrement that is then undone.
-__device__ __forceinline__ i32 psl_rule(i32 x, i32 y, i32 e1, i32 l, i32* S, u8* state, int owner_higher) {
+// seen from frontier edge e1 in round r: x loses one unit if its support is
+// above l and e1 owns the triangle (y is not in the frontier, or e1 has the
+// lower id -- the higher id with owner_higher).  The atomic's old value decides:
+// l + 1 means x now sits at l and joins the next frontier (tag of round r + 1); <= l
+// means the decrement overshot (another thread got there first) and is undone.
+// Returns x if it joined the next frontier, else -1.  The plain pre-read of S
+// may be stale: while S[x] > l every older value is > l too, and once S[x] <= l
+// it stays <= l for the level, so a stale read can only cause a decrement that
+// is then undone.  The next-frontier tag written here reads as "not current"
+// and "not processed" to every other thread of the round, as it should.
+__device__ __forceinline__ i32 psl_rule(i32 x, i32 y, i32 e1, i32 l, i32 r, i32* S, u8* state, int owner_higher) {
   if (atomic_load_relaxed(&S[x]) <= l) return -1;
-  const bool y_curr = state[y] == ST_CURR;
+  const bool y_curr = state[y] == round_tag(r);
   const bool mine = !y_curr || (owner_higher ? (e1 > y) : (e1 < y));
   if (!mine) return -1;
   const i32 a = atomicSub(&S[x], 1);
   if (a == l + 1) {
-    state[x] = ST_NEXT;
+    state[x] = round_tag(r + 1);
     return x;
   }
   if (a <= l) atomicAdd(&S[x], 1);
@@ -113,7 +120,7 @@ __device__ __forceinline__ int log2_bin(i64 d) { return 63 - __clzll((unsigned l
 #define FEAT_SAMPLE 512  // frontier edges sampled (evenly spaced) for the features
 
 __device__ __forceinline__ bool is_fused(int c) { return c == TRUSS_CHOICE_FUSED || c == TRUSS_CHOICE_FUSED_NARROW; }
-__device__ __forceinline__ bool is_wide(int c) { return !is_fused(c); }
+__device__ __forceinline__ bool is_wide(int c) { return c >= TRUSS_CHOICE_WIDE && c < TRUSS_NUM_CHOICES; }
 
 // The built-in heuristic: fused launch up to FUSED_THRESHOLD frontier edges (the
 // threshold the tuner's trace search picked), else the wide sequence.
@@ -138,7 +145,7 @@ __device__ void decide(const PeelArgs& a, float* sx, float* sy, float* ha, float
     }
     __syncthreads();
     const i32 nc = ctl->ncurr;
-    const i32* curr = ctl->sel ? a.F1 : a.F0;
+    const i32* curr = cur_of(a, ctl->sel);
     const Csr c = a.csr.pick(ctl->csel);
     const i32 ns = min(nc, FEAT_SAMPLE);
     i64 sd = 0, sm = 0, cnt = 0;
@@ -209,6 +216,7 @@ __device__ void decide(const PeelArgs& a, float* sx, float* sy, float* ha, float
       if (best >= 0) c = best;  // otherwise the heuristic stands
     }
     ctl->choice = c;
+    ctl->chosen[c] += 1;
     ctl->variant = (policy == TRUSS_VARIANT_MERGE || c == TRUSS_CHOICE_WIDE_GALLOP) ? TRUSS_VARIANT_MERGE
                                                                                      : TRUSS_VARIANT_BSEARCH;
     for (int i = 0; i < 8; ++i) ctl->feat[i] = i < TRUSS_NUM_FEATURES ? sx[i] : 0.f;
@@ -221,9 +229,10 @@ __device__ void decide(const PeelArgs& a, float* sx, float* sy, float* ha, float
 
 // Item t of frontier edge e1: chunk t of the shorter row, located in the
 // longer row; for every triangle found with no processed edge, the decrement
-// rule on both other edges.  Edges that reached l come back in x0, x1 for a
-// wave-aggregated append; more than two from one item are appended at once.
-__device__ __forceinline__ void psl_item(const PeelArgs& a, const Csr& c, i32 e1, i64 t, i32 l, int variant,
+// rule on both other edges (rd: the round index).  Edges that reached l come
+// back in x0, x1 for a wave-aggregated append; more than two from one item are
+// appended at once.
+__device__ __forceinline__ void psl_item(const PeelArgs& a, const Csr& c, i32 e1, i64 t, i32 l, i32 rd, int variant,
                                          i32& x0, i32& x1, i32* spill_next, i32* spill_ctr) {
   const Rows r = rows_of(c, a.el[e1]);
   const i64 k = chunk_of(variant);
@@ -231,16 +240,16 @@ __device__ __forceinline__ void psl_item(const PeelArgs& a, const Csr& c, i32 e1
   i64 p = r.lb;
   for (i64 j = j0; j < j1; ++j) {
     const i32 es = c.eid[j];
-    if (a.state[es] == ST_PROC) continue;
+    if (is_processed(a.state[es], rd)) continue;
     const i32 w = c.adj[j];
     p = (j == j0) ? lower_bound_dev(c.adj, p, r.le, w) : gallop(c.adj, p, r.le, w);
     if (p == r.le) break;
     if (c.adj[p] != w) continue;
     const i32 eo = c.eid[p];
     ++p;
-    if (a.state[eo] == ST_PROC) continue;
-    const i32 y[2] = {psl_rule(es, eo, e1, l, a.S, a.state, a.owner_higher),
-                      psl_rule(eo, es, e1, l, a.S, a.state, a.owner_higher)};
+    if (is_processed(a.state[eo], rd)) continue;
+    const i32 y[2] = {psl_rule(es, eo, e1, l, rd, a.S, a.state, a.owner_higher),
+                      psl_rule(eo, es, e1, l, rd, a.S, a.state, a.owner_higher)};
     for (int q = 0; q < 2; ++q) {
       if (y[q] < 0) continue;
       if (x0 < 0)
@@ -268,7 +277,8 @@ __device__ __forceinline__ void ctl_after_sublevel(Ctl* ctl, i32 nc, i32 nn, i32
   ctl->processed += nc;
   ctl->ncurr = nn;
   ctl->nnext = 0;
-  ctl->sel = sel ^ 1;
+  ctl->nprev = nc;
+  ctl->sel = sel == 2 ? 0 : sel + 1;
   ctl->sublevels += 1;
   if (nn == 0) ctl->level += 1;
 }
@@ -329,12 +339,12 @@ __device__ __forceinline__ void stable_tile(u32 tk, u32 kp, i32* pt, i32* pk, i3
 }
 
 // Level scan over tiles of the alive list (tiles tile0, tile0 + tstride, ...):
-// edges still unprocessed with support l join the frontier and turn CURR;
-// other unprocessed edges are copied to the other alive list; processed edges
+// edges still alive with support l join the frontier of round r (its tag);
+// other alive edges are copied to the other alive list; edges no longer alive
 // drop out.  Stable (entry order kept); one atomic per counter per tile of NT *
 // SCAN_ITEMS entries (used by a single block, so the atomics are uncontended).
 template <int NT>
-__device__ void scan_tiles(const PeelArgs& a, i32 l, i32 na, const i32* __restrict__ A, i32* __restrict__ Aout,
+__device__ void scan_tiles(const PeelArgs& a, i32 l, i32 r, i32 na, const i32* __restrict__ A, i32* __restrict__ Aout,
                            i32* __restrict__ curr, i64 tile0, i64 tstride, i32& mn, i64* tmp, i64* cnt, i32* sbase) {
   const i64 tile = (i64)NT * SCAN_ITEMS;
   for (i64 t0 = tile0 * tile; t0 < na; t0 += tstride * tile) {
@@ -376,7 +386,7 @@ __device__ void scan_tiles(const PeelArgs& a, i32 l, i32 na, const i32* __restri
     for (int k = 0; k < SCAN_ITEMS; ++k) {
       if ((tk >> k) & 1u) {
         curr[sbase[0] + pt[k]] = ev[k];
-        a.state[ev[k]] = ST_CURR;
+        a.state[ev[k]] = round_tag(r);
       } else if ((kp >> k) & 1u) {
         Aout[sbase[1] + pk[k]] = ev[k];
       }
@@ -385,11 +395,11 @@ __device__ void scan_tiles(const PeelArgs& a, i32 l, i32 na, const i32* __restri
   }
 }
 
-// Marks the end of a round: frontier edges processed, next ones current.
-__device__ __forceinline__ void mark_states(const PeelArgs& a, const i32* curr, i32 nc, const i32* next, i32 nn,
-                                            i64 tid, i64 stride) {
-  for (i64 i = tid; i < nc; i += stride) a.state[curr[i]] = ST_PROC;
-  for (i64 i = tid; i < nn; i += stride) a.state[next[i]] = ST_CURR;
+// The previous round's frontier turns processed (its tag is handed out again by
+// the next round); every block of a round takes a strided share.
+__device__ __forceinline__ void mark_prev(const PeelArgs& a, int sel, i32 nprev, i64 tid, i64 stride) {
+  const i32* prev = prev_of(a, sel);
+  for (i64 i = tid; i < nprev; i += stride) a.state[prev[i]] = ST_PROC;
 }
 
 // Exclusive prefix of the work of frontier edges [0, nc) into LDS P[0..nc]
@@ -422,14 +432,14 @@ __device__ i64 lds_work_prefix(const PeelArgs& a, const Csr& c, const i32* curr,
 
 // Items [base, total) with the given stride, pairs located through LDS P.
 template <int NT>
-__device__ void lds_items(const PeelArgs& a, const Csr& c, const i32* curr, i32 nc, i32 l, int variant, const i64* P,
-                          i64 total, i64 base, i64 stride, i32* next) {
+__device__ void lds_items(const PeelArgs& a, const Csr& c, const i32* curr, i32 nc, i32 l, i32 r, int variant,
+                          const i64* P, i64 total, i64 base, i64 stride, i32* next) {
   for (i64 b = base; b < total; b += stride) {
     const i64 g = b + threadIdx.x;
     i32 x0 = -1, x1 = -1;
     if (g < total) {
       const i64 i = upper_bound_dev(P, (i64)0, (i64)nc + 1, g) - 1;
-      psl_item(a, c, curr[i], g - P[i], l, variant, x0, x1, next, &a.ctl->nnext);
+      psl_item(a, c, curr[i], g - P[i], l, r, variant, x0, x1, next, &a.ctl->nnext);
     }
     append_next(x0, x1, next, &a.ctl->nnext);
   }
@@ -437,7 +447,7 @@ __device__ void lds_items(const PeelArgs& a, const Csr& c, const i32* curr, i32 
 
 // Snapshot of the control block shared through LDS by one block.
 struct CtlView {
-  i32 done, ncurr, level, sel, csel, nalive, asel, variant, choice;
+  i32 done, ncurr, level, sel, csel, nalive, asel, variant, choice, r, nprev;
 };
 
 __device__ __forceinline__ void load_view(const Ctl* ctl, CtlView* v) {
@@ -451,16 +461,19 @@ __device__ __forceinline__ void load_view(const Ctl* ctl, CtlView* v) {
     v->asel = ctl->asel;
     v->variant = ctl->variant;
     v->choice = ctl->choice;
+    v->r = ctl->sublevels;
+    v->nprev = ctl->nprev;
   }
   __syncthreads();
 }
 
-// Last-arriving-block detection (every block calls it once, all threads).
-__device__ __forceinline__ bool arrive_last(Ctl* ctl, int* slast) {
+// Last-arriving-block detection among nblk blocks (each calls it once, all
+// threads).
+__device__ __forceinline__ bool arrive_last(Ctl* ctl, int* slast, int nblk) {
   __syncthreads();
   if (threadIdx.x == 0) {
     __threadfence();
-    *slast = (atomicAdd(&ctl->arrive, 1u) == gridDim.x - 1);
+    *slast = (atomicAdd(&ctl->arrive, 1u) == (u32)nblk - 1);
   }
   __syncthreads();
   const bool last = *slast;
@@ -470,13 +483,84 @@ __device__ __forceinline__ bool arrive_last(Ctl* ctl, int* slast) {
 
 }  // namespace
 
+// ---------------------------------------------------------------- single block
+
+namespace {
+
+// LDS of a block that may go on alone (P: work prefix of a small frontier).
+template <int NT>
+struct AloneLds {
+  i64 P[SMALL_FRONTIER + 1];
+  i64 tmp[NT / PKT_WAVE];
+  i64 cnt[SCAN_ITEMS * (NT / PKT_WAVE)];
+  i32 sbase[2];
+  i32 nn;
+  CtlView v;
+};
+
+// The last block of a round or level scan goes on alone while the work stays
+// small: rounds of at most ALONE_FRONTIER edges and ALONE_ITEMS items, and level
+// scans of at most ALONE_ALIVE entries.  It stops at once with single_round.
+// On return the control block says what is left (ncurr > 0: a frontier whose
+// launch is still to be picked; ncurr == 0: a level scan; or done).
+template <int NT>
+__device__ void go_alone(const PeelArgs& a, AloneLds<NT>& s) {
+  Ctl* ctl = a.ctl;
+  if (a.single_round) return;
+  for (int iter = 0; iter < (1 << 20); ++iter) {
+    load_view(ctl, &s.v);
+    if (s.v.done) break;
+    const i32 l = s.v.level, sel = s.v.sel, r = s.v.r;
+    i32* curr = cur_of(a, sel);
+    if (s.v.ncurr == 0) {
+      if (s.v.nalive > ALONE_ALIVE) break;
+      const i32* A = s.v.asel ? a.A1 : a.A0;
+      i32* Aout = s.v.asel ? a.A0 : a.A1;
+      i32 mn = INT_MAX;
+      scan_tiles<NT>(a, l, r, s.v.nalive, A, Aout, curr, 0, 1, mn, s.tmp, s.cnt, s.sbase);
+      mn = wave_min_i32(mn);
+      if (lane_id() == 0 && mn != INT_MAX) atomicMin(&ctl->min_above, mn);
+      __syncthreads();  // every wave's minimum is in before thread 0 reads it
+      if (threadIdx.x == 0)
+        ctl_after_scan(ctl, atomicAdd(&ctl->nfound, 0), atomicAdd(&ctl->nalive_out, 0),
+                       atomicAdd(&ctl->min_above, 0), s.v.asel);
+      __syncthreads();
+      continue;
+    }
+    if (s.v.ncurr > ALONE_FRONTIER) break;
+    const Csr c = a.csr.pick(s.v.csel);
+    i32* next = next_of(a, sel);
+    const i64 total = lds_work_prefix<NT>(a, c, curr, s.v.ncurr, l, s.v.variant, s.P, s.tmp);
+    if (total > ALONE_ITEMS) break;
+    mark_prev(a, sel, s.v.nprev, threadIdx.x, NT);
+    lds_items<NT>(a, c, curr, s.v.ncurr, l, r, s.v.variant, s.P, total, 0, NT, next);
+    __syncthreads();  // every wave's appends are counted before the count is read
+    if (threadIdx.x == 0) ctl_after_sublevel(ctl, s.v.ncurr, atomicAdd(&ctl->nnext, 0), sel);
+    __syncthreads();
+  }
+}
+
+// End of a round or level scan in its last block: go on alone, then pick the
+// launch of the frontier left, if any.
+template <int NT>
+__device__ void leave(const PeelArgs& a, AloneLds<NT>& s) {
+  go_alone<NT>(a, s);
+  __shared__ float sx[8], sy[MLP_OUT], ha[MLP_H], hb[MLP_H];
+  __shared__ int schoice;
+  load_view(a.ctl, &s.v);
+  if (!s.v.done && s.v.ncurr > 0) decide(a, sx, sy, ha, hb, &schoice);
+}
+
+}  // namespace
+
 // ---------------------------------------------------------------- kernels
 
-// Level scan in three passes, with no contended atomics: every block counts the
-// taken and kept entries of its contiguous chunk of the alive list (pass 1), one
-// block turns the counts into offsets (pass 2), every block writes its entries at
-// its offset (pass 3, whose last block updates the control block and decides the
-// first round's launch).  Chunks: G blocks of ceil(na / G) entries, tile-aligned.
+// Level scan in two launches, with no contended atomics: every block counts the
+// taken and kept entries of its contiguous chunk of the alive list, and the last
+// block to finish turns the counts into offsets (k_scan_count); every block then
+// writes its entries at its offset, and the last one updates the control block
+// and goes on (k_scan_write).  Chunks: gridDim.x blocks of ceil(na / gridDim.x)
+// entries, tile-aligned; blocks past the end count nothing.
 namespace {
 __device__ __forceinline__ void scan_chunk(i32 na, int G, i64* c0, i64* c1) {
   const i64 tile = (i64)PKT_BLOCK * SCAN_ITEMS;
@@ -516,14 +600,12 @@ __device__ __forceinline__ void classify(const PeelArgs& a, i32 l, const i32* __
     }
   }
 }
-
-__device__ __forceinline__ bool scan_gate(const Ctl* ctl) { return !ctl->done && ctl->ncurr == 0 && !ctl->scan_pending; }
 }  // namespace
 
-__global__ __launch_bounds__(PKT_BLOCK) void k_scan_count(PeelArgs a, int G, i64* __restrict__ part,
-                                                         i32* __restrict__ bmin) {
-  const Ctl* ctl = a.ctl;
-  if (!scan_gate(ctl)) return;
+__global__ __launch_bounds__(PKT_BLOCK) void k_scan_count(PeelArgs a, i64* __restrict__ part, i32* __restrict__ bmin) {
+  Ctl* ctl = a.ctl;
+  if (ctl->done || ctl->ncurr != 0 || ctl->scan_pending) return;
+  const int G = gridDim.x;
   const i32 l = ctl->level, na = ctl->nalive;
   const i32* A = ctl->asel ? a.A1 : a.A0;
   i64 c0, c1;
@@ -538,6 +620,7 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_scan_count(PeelArgs a, int G, i64
   }
   __shared__ i64 sp[PKT_BLOCK / PKT_WAVE];
   __shared__ i32 sm[PKT_BLOCK / PKT_WAVE];
+  __shared__ int last;
   packed = wave_sum_i64(packed);
   mn = wave_min_i32(mn);
   if (lane_id() == 0) {
@@ -555,22 +638,16 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_scan_count(PeelArgs a, int G, i64
     part[blockIdx.x] = t;
     bmin[blockIdx.x] = m;
   }
-}
-
-__global__ __launch_bounds__(PKT_BLOCK) void k_scan_offsets(PeelArgs a, int G, i64* __restrict__ part,
-                                                           const i32* __restrict__ bmin) {
-  Ctl* ctl = a.ctl;
-  if (!scan_gate(ctl)) return;
-  __shared__ i64 tmp[PKT_BLOCK / PKT_WAVE];
-  __shared__ i32 sm[PKT_BLOCK / PKT_WAVE];
+  if (!arrive_last(ctl, &last, G)) return;
+  // last block: chunk counts -> offsets; totals and the minimum kept support
   i64 running = 0;
-  i32 mn = INT_MAX;
+  mn = INT_MAX;
   for (int base = 0; base < G; base += PKT_BLOCK) {
     const int i = base + threadIdx.x;
     const i64 v = (i < G) ? part[i] : 0;
     if (i < G) mn = min(mn, bmin[i]);
     i64 tot;
-    const i64 ex = block_excl_scan_i64(v, tmp, &tot);
+    const i64 ex = block_excl_scan_i64(v, sp, &tot);
     if (i < G) part[i] = running + ex;
     running += tot;
   }
@@ -583,20 +660,21 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_scan_offsets(PeelArgs a, int G, i
     ctl->nalive_out = (i32)(running & 0xffffffffll);
     ctl->min_above = mn;
     ctl->scan_pending = 1;
+    ctl->arrive = 0;
   }
 }
 
-__global__ __launch_bounds__(PKT_BLOCK) void k_scan_write(PeelArgs a, int G, const i64* __restrict__ part) {
+__global__ __launch_bounds__(PKT_BLOCK) void k_scan_write(PeelArgs a, const i64* __restrict__ part) {
   Ctl* ctl = a.ctl;
   if (ctl->done || !ctl->scan_pending) return;
-  const i32 l = ctl->level, na = ctl->nalive, asel = ctl->asel;
+  const int G = gridDim.x;
+  const i32 l = ctl->level, na = ctl->nalive, asel = ctl->asel, r = ctl->sublevels;
   const i32* A = asel ? a.A1 : a.A0;
   i32* Aout = asel ? a.A0 : a.A1;
-  i32* curr = ctl->sel ? a.F1 : a.F0;
+  i32* curr = cur_of(a, ctl->sel);
   __shared__ i64 tmp[PKT_BLOCK / PKT_WAVE];
   __shared__ i64 cnt[SCAN_ITEMS * (PKT_BLOCK / PKT_WAVE)];
-  __shared__ int last, schoice;
-  __shared__ float sx[8], sy[MLP_OUT], ha[MLP_H], hb[MLP_H];
+  __shared__ int last;
   i64 c0, c1;
   scan_chunk(na, G, &c0, &c1);
   const i64 base = part[blockIdx.x];
@@ -612,7 +690,7 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_scan_write(PeelArgs a, int G, con
     for (int k = 0; k < SCAN_ITEMS; ++k) {
       if ((tk >> k) & 1u) {
         curr[bt + pt[k]] = ev[k];
-        a.state[ev[k]] = ST_CURR;
+        a.state[ev[k]] = round_tag(r);
       } else if ((kp >> k) & 1u) {
         Aout[bk + pk[k]] = ev[k];
       }
@@ -620,90 +698,40 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_scan_write(PeelArgs a, int G, con
     bt += nt;
     bk += nk;
   }
-  if (!arrive_last(ctl, &last)) return;
+  if (!arrive_last(ctl, &last, G)) return;
   if (threadIdx.x == 0) {
     ctl_after_scan(ctl, ctl->nfound, ctl->nalive_out, ctl->min_above, asel);
     ctl->scan_pending = 0;
+    ctl->choice = CHOICE_NONE;  // k_decide follows
     ctl->arrive = 0;
   }
-  __syncthreads();
-  if (ctl->ncurr > 0) decide(a, sx, sy, ha, hb, &schoice);
 }
 
+// A whole round of a frontier of at most SMALL_FRONTIER edges: every block
+// builds the frontier's work prefix in LDS and takes its share of the items
+// (k_decide follows and ends the round).
+// TRUSS_CHOICE_FUSED_NARROW uses the first FUSED_NARROW_BLOCKS blocks of the grid.
 __global__ __launch_bounds__(SMALL_THREADS) void k_psl_small(PeelArgs a) {
   Ctl* ctl = a.ctl;
   __shared__ i64 P[SMALL_FRONTIER + 1];
   __shared__ i64 tmp[SMALL_THREADS / PKT_WAVE];
-  __shared__ i64 scnt[SCAN_ITEMS * (SMALL_THREADS / PKT_WAVE)];
-  __shared__ i32 sbase[2];
   __shared__ CtlView v;
-  __shared__ int last, schoice;
-  __shared__ i32 s_nn;
-  __shared__ float sx[8], sy[MLP_OUT], ha[MLP_H], hb[MLP_H];
   load_view(ctl, &v);
   if (v.done || v.ncurr == 0 || v.ncurr > SMALL_FRONTIER || !is_fused(v.choice)) return;
-  {
-    const i32 nc = v.ncurr, l = v.level, sel = v.sel;
-    const Csr c = a.csr.pick(v.csel);
-    const i32* curr = sel ? a.F1 : a.F0;
-    i32* next = sel ? a.F0 : a.F1;
-    const i64 total = lds_work_prefix<SMALL_THREADS>(a, c, curr, nc, l, v.variant, P, tmp);
-    lds_items<SMALL_THREADS>(a, c, curr, nc, l, v.variant, P, total, (i64)blockIdx.x * SMALL_THREADS,
-                             (i64)gridDim.x * SMALL_THREADS, next);
-    if (!arrive_last(ctl, &last)) return;
-    if (threadIdx.x == 0) s_nn = atomicAdd(&ctl->nnext, 0);
-    __syncthreads();
-    const i32 nn = s_nn;
-    mark_states(a, curr, nc, next, nn, threadIdx.x, SMALL_THREADS);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      ctl_after_sublevel(ctl, nc, nn, sel);
-      ctl->arrive = 0;
-    }
-    __syncthreads();
-  }
-  // The last block goes on alone while the work stays small: tiny rounds, and
-  // level scans over a short alive list.  On leaving with a frontier, it picks
-  // the launch of that frontier's round.
-  for (int iter = 0; iter < (1 << 20); ++iter) {
-    load_view(ctl, &v);
-    if (v.done) break;
-    const i32 l = v.level, sel = v.sel;
-    i32* curr = (i32*)(sel ? a.F1 : a.F0);
-    if (v.ncurr == 0) {
-      if (a.single_round || v.nalive > ALONE_ALIVE) break;
-      const i32* A = v.asel ? a.A1 : a.A0;
-      i32* Aout = v.asel ? a.A0 : a.A1;
-      i32 mn = INT_MAX;
-      scan_tiles<SMALL_THREADS>(a, l, v.nalive, A, Aout, curr, 0, 1, mn, tmp, scnt, sbase);
-      mn = wave_min_i32(mn);
-      if (lane_id() == 0 && mn != INT_MAX) atomicMin(&ctl->min_above, mn);
-      __syncthreads();  // every wave's minimum is in before thread 0 reads it
-      if (threadIdx.x == 0)
-        ctl_after_scan(ctl, atomicAdd(&ctl->nfound, 0), atomicAdd(&ctl->nalive_out, 0),
-                       atomicAdd(&ctl->min_above, 0), v.asel);
-      __syncthreads();
-      continue;
-    }
-    if (a.single_round || v.ncurr > ALONE_FRONTIER) break;
-    const Csr c = a.csr.pick(v.csel);
-    i32* next = (i32*)(sel ? a.F0 : a.F1);
-    const i64 total = lds_work_prefix<SMALL_THREADS>(a, c, curr, v.ncurr, l, v.variant, P, tmp);
-    if (total > ALONE_ITEMS) break;
-    lds_items<SMALL_THREADS>(a, c, curr, v.ncurr, l, v.variant, P, total, 0, SMALL_THREADS, next);
-    __syncthreads();  // every wave's appends are counted before the count is read
-    if (threadIdx.x == 0) s_nn = atomicAdd(&ctl->nnext, 0);
-    __syncthreads();
-    mark_states(a, curr, v.ncurr, next, s_nn, threadIdx.x, SMALL_THREADS);
-    __syncthreads();
-    if (threadIdx.x == 0) ctl_after_sublevel(ctl, v.ncurr, s_nn, sel);
-    __syncthreads();
-  }
-  load_view(ctl, &v);
-  if (!v.done && v.ncurr > 0) decide(a, sx, sy, ha, hb, &schoice);
+  const int nblk = v.choice == TRUSS_CHOICE_FUSED_NARROW ? min((int)gridDim.x, FUSED_NARROW_BLOCKS) : gridDim.x;
+  if ((int)blockIdx.x >= nblk) return;
+  const i32 nc = v.ncurr, l = v.level, sel = v.sel, r = v.r;
+  const Csr c = a.csr.pick(v.csel);
+  const i32* curr = cur_of(a, sel);
+  i32* next = next_of(a, sel);
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->round_done = 1;
+  mark_prev(a, sel, v.nprev, (i64)blockIdx.x * SMALL_THREADS + threadIdx.x, (i64)nblk * SMALL_THREADS);
+  const i64 total = lds_work_prefix<SMALL_THREADS>(a, c, curr, nc, l, v.variant, P, tmp);
+  lds_items<SMALL_THREADS>(a, c, curr, nc, l, r, v.variant, P, total, (i64)blockIdx.x * SMALL_THREADS,
+                           (i64)nblk * SMALL_THREADS, next);
 }
 
-// Work of frontier edge i for the device-wide scan (wide rounds).
+// Work of frontier edge i for the device-wide scan (wide rounds above level 0).
 struct WideLen {
   PeelArgs a;
   __device__ bool active() const {
@@ -713,29 +741,43 @@ struct WideLen {
   __device__ i64 count() const { return a.ctl->ncurr; }
   __device__ i64 len(i64 i) const {
     const Ctl* c = a.ctl;
-    const i32* curr = c->sel ? a.F1 : a.F0;
+    const i32* curr = cur_of(a, c->sel);
     return work_of(a, a.csr.pick(c->csel), curr[i], c->level, c->variant);
   }
 };
 
-__global__ __launch_bounds__(PKT_BLOCK) void k_psl_bsearch(WideLen f, const i64* __restrict__ P) {
-  if (!f.active()) return;
-  const PeelArgs& a = f.a;
+// Wide round: one thread per intersection item over the whole grid, items
+// located through the device-wide work prefix P (not read at level 0, where
+// there are no items); k_decide follows and ends the round.
+// TRUSS_CHOICE_WIDE_NARROW uses the first WIDE_NARROW_BLOCKS blocks.  Kept
+// lean: its register count sets the occupancy of the item loop, and no block
+// fences or counts arrivals (a device-scope fence per block costs more than the
+// kernel boundary that orders the round's end).
+__global__ __launch_bounds__(PKT_BLOCK) void k_psl_bsearch(PeelArgs a, const i64* __restrict__ P) {
   Ctl* ctl = a.ctl;
+  __shared__ CtlView v;
   __shared__ i64 sp[2];
-  const i64 npairs = ctl->ncurr;
-  const i64 total = P[npairs];
-  const i32 l = ctl->level;
-  const int variant = ctl->variant;
-  const i32* curr = ctl->sel ? a.F1 : a.F0;
-  i32* next = ctl->sel ? a.F0 : a.F1;
-  const Csr c = a.csr.pick(ctl->csel);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {  // accounting for the roofline report
-    atomicAdd((unsigned long long*)&ctl->wide_items, (unsigned long long)total);
-    atomicAdd((unsigned long long*)&ctl->wide_frontier, (unsigned long long)npairs);
-    atomicAdd(&ctl->wide_launches, 1);
+  load_view(ctl, &v);
+  if (v.done || v.ncurr == 0 || !is_wide(v.choice)) return;
+  const int nblk = v.choice == TRUSS_CHOICE_WIDE_NARROW ? min((int)gridDim.x, WIDE_NARROW_BLOCKS) : gridDim.x;
+  if ((int)blockIdx.x >= nblk) return;
+  const i32 nc = v.ncurr, l = v.level, sel = v.sel, r = v.r;
+  const i64 npairs = nc;
+  const i64 total = l > 0 ? P[npairs] : 0;
+  const int variant = v.variant;
+  const i32* curr = cur_of(a, sel);
+  i32* next = next_of(a, sel);
+  const Csr c = a.csr.pick(v.csel);
+  mark_prev(a, sel, v.nprev, (i64)blockIdx.x * PKT_BLOCK + threadIdx.x, (i64)nblk * PKT_BLOCK);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl->round_done = 1;
+    if (total > 0) {  // accounting for the roofline report
+      ctl->wide_items += total;
+      ctl->wide_frontier += npairs;
+      ctl->wide_launches += 1;
+    }
   }
-  for (i64 base = (i64)blockIdx.x * PKT_BLOCK; base < total; base += (i64)gridDim.x * PKT_BLOCK) {
+  for (i64 base = (i64)blockIdx.x * PKT_BLOCK; base < total; base += (i64)nblk * PKT_BLOCK) {
     if (threadIdx.x == 0) sp[0] = upper_bound_dev(P, (i64)0, npairs + 1, base) - 1;
     if (threadIdx.x == PKT_WAVE)
       sp[1] = upper_bound_dev(P, (i64)0, npairs + 1, min(base + PKT_BLOCK, total) - 1) - 1;
@@ -744,30 +786,34 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_psl_bsearch(WideLen f, const i64*
     i32 x0 = -1, x1 = -1;
     if (g < total) {
       const i64 i = upper_bound_dev(P, sp[0], sp[1] + 1, g) - 1;
-      psl_item(a, c, curr[i], g - P[i], l, variant, x0, x1, next, &ctl->nnext);
+      psl_item(a, c, curr[i], g - P[i], l, r, variant, x0, x1, next, &ctl->nnext);
     }
     append_next(x0, x1, next, &ctl->nnext);
     __syncthreads();
   }
 }
 
-__global__ __launch_bounds__(PKT_BLOCK) void k_finalize(PeelArgs a) {
+// One block after a level scan or a round: ends the round the previous launch
+// ran (Ctl::round_done), goes on alone while the work stays small, then picks
+// the launch of the frontier left, if any (only when none is picked yet).
+__global__ __launch_bounds__(DECIDE_THREADS) void k_decide(PeelArgs a) {
   Ctl* ctl = a.ctl;
-  if (ctl->done || ctl->ncurr == 0 || !is_wide(ctl->choice)) return;
-  const i32 nc = ctl->ncurr, nn = ctl->nnext, sel = ctl->sel;
-  const i32* curr = sel ? a.F1 : a.F0;
-  const i32* next = sel ? a.F0 : a.F1;
-  mark_states(a, curr, nc, next, nn, (i64)blockIdx.x * PKT_BLOCK + threadIdx.x, (i64)gridDim.x * PKT_BLOCK);
-  __shared__ int last, schoice;
-  __shared__ float sx[8], sy[MLP_OUT], ha[MLP_H], hb[MLP_H];
-  if (!arrive_last(ctl, &last)) return;
-  if (threadIdx.x == 0) {
-    ctl_after_sublevel(ctl, nc, nn, sel);
-    ctl->arrive = 0;
+  __shared__ AloneLds<DECIDE_THREADS> s;
+  load_view(ctl, &s.v);
+  if (s.v.done) return;
+  if (ctl->round_done) {
+    if (threadIdx.x == 0) {
+      ctl_after_sublevel(ctl, s.v.ncurr, ctl->nnext, s.v.sel);
+      ctl->round_done = 0;
+      ctl->choice = CHOICE_NONE;
+    }
+    __syncthreads();
+  } else if (s.v.choice != CHOICE_NONE) {
+    return;
   }
-  __syncthreads();
-  if (ctl->ncurr > 0) decide(a, sx, sy, ha, hb, &schoice);
+  leave<DECIDE_THREADS>(a, s);
 }
+
 
 // ---------------------------------------------------------------- host side
 
@@ -848,8 +894,7 @@ struct KernelClock {
 PeelArgs peel_args(const Work& w, const truss_options& opt) {
   PeelArgs a;
   a.ctl = w.ctl;
-  a.F0 = w.F[0];
-  a.F1 = w.F[1];
+  for (int k = 0; k < 3; ++k) a.F[k] = w.F[k];
   a.A0 = w.A[0];
   a.A1 = w.A[1];
   a.el = w.el;
@@ -863,36 +908,103 @@ PeelArgs peel_args(const Work& w, const truss_options& opt) {
   return a;
 }
 
-// One launch sequence for the current loop state (read into hc): a level scan,
-// or the round of the current frontier as its launch choice says.
+// Grid of a level scan over nalive entries: one block per tile, at most SCAN_BLOCKS.
+inline int scan_grid(i64 nalive) {
+  const i64 tiles = (nalive + (i64)PKT_BLOCK * SCAN_ITEMS - 1) / ((i64)PKT_BLOCK * SCAN_ITEMS);
+  return (int)(tiles < 1 ? 1 : (tiles > SCAN_BLOCKS ? SCAN_BLOCKS : tiles));
+}
+
+// Host-driven loop: the launch sequence for the current loop state (read into
+// hc): a level scan, or the round of the current frontier as its launch choice
+// says.
 static truss_status launch_round(const Work& w, const PeelArgs& a, const Ctl& hc, hipStream_t s, int* kind,
                                  KernelClock* prof) {
   if (hc.ncurr == 0) {
     *kind = 0;
-    const i64 tiles = ((i64)hc.nalive + (i64)PKT_BLOCK * SCAN_ITEMS - 1) / ((i64)PKT_BLOCK * SCAN_ITEMS);
-    const int G = (int)(tiles < 1 ? 1 : (tiles > SCAN_BLOCKS ? SCAN_BLOCKS : tiles));
-    hipLaunchKernelGGL(k_scan_count, dim3(G), dim3(PKT_BLOCK), 0, s, a, G, w.partial, w.bmin);
-    hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(PKT_BLOCK), 0, s, a, G, w.partial, (const i32*)w.bmin);
-    hipLaunchKernelGGL(k_scan_write, dim3(G), dim3(PKT_BLOCK), 0, s, a, G, (const i64*)w.partial);
+    const int G = scan_grid(hc.nalive);
+    hipLaunchKernelGGL(k_scan_count, dim3(G), dim3(PKT_BLOCK), 0, s, a, w.partial, w.bmin);
+    hipLaunchKernelGGL(k_scan_write, dim3(G), dim3(PKT_BLOCK), 0, s, a, (const i64*)w.partial);
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a);
+  } else if (hc.choice == CHOICE_NONE) {
+    *kind = 0;
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a);
   } else if (hc.choice == TRUSS_CHOICE_FUSED || hc.choice == TRUSS_CHOICE_FUSED_NARROW) {
     *kind = 1;
     const int blocks = hc.choice == TRUSS_CHOICE_FUSED ? FUSED_BLOCKS : FUSED_NARROW_BLOCKS;
     hipLaunchKernelGGL(k_psl_small, dim3(blocks), dim3(SMALL_THREADS), 0, s, a);
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a);
   } else {
     *kind = 2;
-    if (hc.level > 0) {  // level 0: frontier edges lie in no triangle, nothing to intersect
-      WideLen f{a};
-      PKT_HIP(scan_launch(f, w.partial, w.X, s));
-      const int blocks = hc.choice == TRUSS_CHOICE_WIDE_NARROW ? WIDE_NARROW_BLOCKS : WIDE_BLOCKS;
-      if (prof) PKT_HIP(prof->mark(s));
-      hipLaunchKernelGGL(k_psl_bsearch, dim3(blocks), dim3(PKT_BLOCK), 0, s, f, (const i64*)w.X);
-      if (prof) PKT_HIP(prof->mark(s));
-    }
-    hipLaunchKernelGGL(k_finalize, dim3(grid_for(hc.ncurr, 1024)), dim3(PKT_BLOCK), 0, s, a);
+    // level 0: frontier edges lie in no triangle, nothing to intersect or scan
+    if (hc.level > 0) PKT_HIP(scan_launch(WideLen{a}, w.partial, w.X, &w.ctl->scan_arrive, s));
+    const int blocks = hc.choice == TRUSS_CHOICE_WIDE_NARROW ? WIDE_NARROW_BLOCKS : WIDE_BLOCKS;
+    const bool timed = prof && hc.level > 0;
+    if (timed) PKT_HIP(prof->mark(s));
+    hipLaunchKernelGGL(k_psl_bsearch, dim3(blocks), dim3(PKT_BLOCK), 0, s, a, (const i64*)w.X);
+    if (timed) PKT_HIP(prof->mark(s));
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a);
   }
   PKT_LAUNCH_CHECK();
   return TRUSS_OK;
 }
+
+// Device-driven loop: one step is every launch any loop state can need, each
+// gated on the control block, so a step advances the loop by a level scan
+// and/or a round (more when a last block goes on alone) without the host
+// reading anything.  Launches whose gate is closed return at once.  The first
+// k_decide ends the previous step's wide round.
+static truss_status enqueue_step(const Work& w, const PeelArgs& a, int G, hipStream_t s, KernelClock* prof) {
+  hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a);
+  hipLaunchKernelGGL(k_scan_count, dim3(G), dim3(PKT_BLOCK), 0, s, a, w.partial, w.bmin);
+  hipLaunchKernelGGL(k_scan_write, dim3(G), dim3(PKT_BLOCK), 0, s, a, (const i64*)w.partial);
+  hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a);
+  hipLaunchKernelGGL(k_psl_small, dim3(FUSED_BLOCKS), dim3(SMALL_THREADS), 0, s, a);
+  hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a);
+  PKT_HIP(scan_launch(WideLen{a}, w.partial, w.X, &w.ctl->scan_arrive, s));
+  if (prof) PKT_HIP(prof->mark(s));
+  hipLaunchKernelGGL(k_psl_bsearch, dim3(WIDE_BLOCKS), dim3(PKT_BLOCK), 0, s, a, (const i64*)w.X);
+  if (prof) PKT_HIP(prof->mark(s));
+  PKT_LAUNCH_CHECK();
+  return TRUSS_OK;
+}
+
+#define GRAPH_STEPS 8  // steps per captured graph
+
+// GRAPH_STEPS steps captured once into a hipGraph and replayed; recaptured when
+// the level-scan grid it was built with no longer fits the alive list.
+struct StepGraph {
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap = nullptr;
+  int G = 0;
+  truss_status ensure(const Work& w, const PeelArgs& a, int want) {
+    if (exec && want <= G && G <= 4 * want) return TRUSS_OK;
+    release();
+    PKT_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    PKT_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    truss_status st = TRUSS_OK;
+    for (int k = 0; k < GRAPH_STEPS && st == TRUSS_OK; ++k) st = enqueue_step(w, a, want, cap, nullptr);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(cap, &g);
+    if (st) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    PKT_HIP(e);
+    const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    PKT_HIP(ei);
+    G = want;
+    return TRUSS_OK;
+  }
+  void release() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (cap) (void)hipStreamDestroy(cap);
+    exec = nullptr;
+    cap = nullptr;
+    G = 0;
+  }
+  ~StepGraph() { release(); }
+};
 
 truss_status run_single(const Work& w, const truss_options& opt, truss_stats* stats, i32* trussness,
                         hipStream_t s, bool support_only) {
@@ -907,6 +1019,7 @@ truss_status run_single(const Work& w, const truss_options& opt, truss_stats* st
   init.policy = opt.variant;
   init.force_choice = opt.force_choice;
   init.variant = opt.variant == TRUSS_VARIANT_MERGE ? TRUSS_VARIANT_MERGE : TRUSS_VARIANT_BSEARCH;
+  init.choice = CHOICE_NONE;
   PKT_HIP(hipMemcpyAsync(w.ctl, &init, sizeof(Ctl), hipMemcpyHostToDevice, s));
   if (opt.validate) {
     truss_status st = validate_input(w, s);
@@ -939,46 +1052,83 @@ truss_status run_single(const Work& w, const truss_options& opt, truss_stats* st
     PKT_HIP(hipEventCreate(&tev[1]));
   }
   KernelClock clock;
-  i64 choice_count[TRUSS_NUM_CHOICES] = {0};
   Ctl hc;
   st = read_ctl(w, &hc, s);
   if (st) return st;
   i64 guard = 0;
-  const i64 guard_max = 4 * w.m + 4096;
-  while (!hc.done) {
-    if (++guard > guard_max) {
-      set_error("level / sub-level count exceeded its bound");
-      return TRUSS_E_INTERNAL;
-    }
-    if (opt.compact && hc.ncurr == 0 && (i64)(w.m - hc.processed) * 2 < (i64)hc.csr_edges) {
-      st = compact(w, s);
+  const i64 guard_max = 4 * w.m + 4096;  // bound on launch sequences / steps
+  // Working-CSR rebuild when under half of its edges are left.  Valid between
+  // any two rounds: rows lose only processed edges, which every round skips.
+  auto maybe_compact = [&]() -> truss_status {
+    if (!opt.compact || (i64)(w.m - hc.processed) * 2 >= (i64)hc.csr_edges) return TRUSS_OK;
+    truss_status r = compact(w, s);
+    if (r) return r;
+    return read_ctl(w, &hc, s);
+  };
+  const int mode = trace ? 0 : opt.device_loop;  // a trace needs one sync per launch sequence
+  if (mode == 0) {
+    while (!hc.done) {
+      if (++guard > guard_max) {
+        set_error("level / sub-level count exceeded its bound");
+        return TRUSS_E_INTERNAL;
+      }
+      st = maybe_compact();
       if (st) return st;
+      const Ctl before = hc;
+      int kind = 0;
+      if (trace) PKT_HIP(hipEventRecord(tev[0], s));
+      st = launch_round(w, a, hc, s, &kind, opt.profile ? &clock : nullptr);
+      if (st) return st;
+      if (trace) PKT_HIP(hipEventRecord(tev[1], s));
       st = read_ctl(w, &hc, s);
       if (st) return st;
+      if (trace && trace->count < trace->capacity) {
+        truss_trace_record& r = trace->records[trace->count++];
+        memset(&r, 0, sizeof(r));
+        r.level = before.level;
+        r.kind = kind;
+        r.choice = kind == 0 ? -1 : before.choice;
+        r.rounds = hc.sublevels - before.sublevels;
+        r.round_index = before.sublevels;
+        r.frontier = before.ncurr;
+        r.items = -1;
+        if (kind == 2 && before.level > 0)
+          PKT_HIP(hipMemcpy(&r.items, w.X + before.ncurr, sizeof(i64), hipMemcpyDeviceToHost));
+        for (int i = 0; i < 8; ++i) r.features[i] = before.feat[i];
+        PKT_HIP(hipEventElapsedTime(&r.ms, tev[0], tev[1]));
+      }
     }
-    const Ctl before = hc;
-    int kind = 0;
-    if (trace) PKT_HIP(hipEventRecord(tev[0], s));
-    st = launch_round(w, a, hc, s, &kind, opt.profile ? &clock : nullptr);
-    if (st) return st;
-    if (trace) PKT_HIP(hipEventRecord(tev[1], s));
-    st = read_ctl(w, &hc, s);
-    if (st) return st;
-    if (kind != 0 && before.choice >= 0 && before.choice < TRUSS_NUM_CHOICES) choice_count[before.choice]++;
-    if (trace && trace->count < trace->capacity) {
-      truss_trace_record& r = trace->records[trace->count++];
-      memset(&r, 0, sizeof(r));
-      r.level = before.level;
-      r.kind = kind;
-      r.choice = kind == 0 ? -1 : before.choice;
-      r.rounds = hc.sublevels - before.sublevels;
-      r.round_index = before.sublevels;
-      r.frontier = before.ncurr;
-      r.items = -1;
-      if (kind == 2 && before.level > 0)
-        PKT_HIP(hipMemcpy(&r.items, w.X + before.ncurr, sizeof(i64), hipMemcpyDeviceToHost));
-      for (int i = 0; i < 8; ++i) r.features[i] = before.feat[i];
-      PKT_HIP(hipEventElapsedTime(&r.ms, tev[0], tev[1]));
+  } else {
+    // Device-driven: batches of steps between host checks (GRAPH_STEPS, doubling
+    // up to 8 * GRAPH_STEPS, or steps_per_sync); with mode 2 the steps replay a
+    // captured hipGraph (not with profile, whose events sit between launches).
+    StepGraph graph;
+    const bool use_graph = mode == 2 && !opt.profile;
+    int batch = 1;
+    while (!hc.done) {
+      st = maybe_compact();
+      if (st) return st;
+      const int G = scan_grid(hc.nalive);
+      const int graphs = opt.steps_per_sync > 0 ? (opt.steps_per_sync + GRAPH_STEPS - 1) / GRAPH_STEPS : batch;
+      const int steps = opt.steps_per_sync > 0 ? opt.steps_per_sync : batch * GRAPH_STEPS;
+      guard += use_graph ? (i64)graphs * GRAPH_STEPS : steps;
+      if (guard > guard_max) {
+        set_error("level / sub-level count exceeded its bound");
+        return TRUSS_E_INTERNAL;
+      }
+      if (use_graph) {
+        st = graph.ensure(w, a, G);
+        if (st) return st;
+        for (int k = 0; k < graphs; ++k) PKT_HIP(hipGraphLaunch(graph.exec, s));
+      } else {
+        for (int k = 0; k < steps; ++k) {
+          st = enqueue_step(w, a, G, s, opt.profile ? &clock : nullptr);
+          if (st) return st;
+        }
+      }
+      st = read_ctl(w, &hc, s);
+      if (st) return st;
+      if (batch < 8) batch *= 2;
     }
   }
   if (trace) {
@@ -1008,11 +1158,12 @@ truss_status run_single(const Work& w, const truss_options& opt, truss_stats* st
     stats->ms_support = tm.ms(2, 3);
     stats->ms_peel = tm.ms(3, 4);
     stats->ms_total = tm.ms(0, 5);
-    for (int k = 0; k < TRUSS_NUM_CHOICES; ++k) stats->choice_count[k] = choice_count[k];
+    for (int k = 0; k < TRUSS_NUM_CHOICES; ++k) stats->choice_count[k] = hc.chosen[k];
     stats->wide_launches = hc.wide_launches;
     stats->wide_items = hc.wide_items;
     stats->wide_frontier = hc.wide_frontier;
     stats->wide_ms = opt.profile ? clock.total_ms() : 0.f;
+    stats->wide_timed = opt.profile ? (i32)(clock.used / 2) : 0;
   }
   return TRUSS_OK;
 }

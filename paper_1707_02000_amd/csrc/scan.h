@@ -1,29 +1,40 @@
 // Device-wide exclusive prefix sums over a count that may live on the device.
 //
-// Reduce-then-scan over a fixed grid of SCAN_BLOCKS workgroups: each block owns
-// one contiguous chunk; pass 1 sums every chunk, pass 2 (one block) scans the
-// chunk sums, pass 3 rescans each chunk from its offset.  The element values
-// come from a functor F with
-//   __device__ bool active() const;   // false: every pass returns at once
+// Reduce-then-scan in two launches over a grid of up to SCAN_BLOCKS workgroups:
+// the count is split into nb contiguous chunks of about SCAN_CHUNK elements
+// (nb <= gridDim.x; blocks past nb return at once).  Pass 1 sums every chunk and
+// its last-arriving block scans the chunk sums; pass 2 rescans each chunk from
+// its offset.  The element values come from a functor F with
+//   __device__ bool active() const;   // false: both passes return at once
 //   __device__ i64  count()  const;   // number of elements
 //   __device__ i64  len(i64 i) const; // value of element i
 // Output: out[i] = sum of len(0..i-1) for i in [0, count], so out[count] is the
-// total.
+// total.  `arrive` is a zeroed counter the last block resets.
 #pragma once
 #include "common.h"
 
 #define SCAN_BLOCKS 1024
+#define SCAN_CHUNK 256  // elements per chunk below SCAN_BLOCKS chunks
+
+__device__ __forceinline__ int scan_nblocks(i64 count) {
+  i64 nb = (count + SCAN_CHUNK - 1) / SCAN_CHUNK;
+  if (nb < 1) nb = 1;
+  return (int)(nb < (i64)gridDim.x ? nb : (i64)gridDim.x);
+}
 
 template <class F>
-__global__ __launch_bounds__(PKT_BLOCK) void k_scan_reduce(F f, i64* __restrict__ partial) {
+__global__ __launch_bounds__(PKT_BLOCK) void k_scan_reduce(F f, i64* __restrict__ partial, u32* __restrict__ arrive) {
   if (!f.active()) return;
   const i64 count = f.count();
-  const i64 chunk = (count + gridDim.x - 1) / gridDim.x;
+  const int nb = scan_nblocks(count);
+  if ((int)blockIdx.x >= nb) return;
+  const i64 chunk = (count + nb - 1) / nb;
   const i64 b0 = (i64)blockIdx.x * chunk;
   const i64 b1 = min(count, b0 + chunk);
   i64 s = 0;
   for (i64 i = b0 + threadIdx.x; i < b1; i += PKT_BLOCK) s += f.len(i);
   __shared__ i64 tmp[PKT_BLOCK / PKT_WAVE];
+  __shared__ int last;
   s = wave_sum_i64(s);
   if (lane_id() == 0) tmp[threadIdx.x / PKT_WAVE] = s;
   __syncthreads();
@@ -31,24 +42,25 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_scan_reduce(F f, i64* __restrict_
     i64 t = 0;
     for (int w = 0; w < PKT_BLOCK / PKT_WAVE; ++w) t += tmp[w];
     partial[blockIdx.x] = t;
+    __threadfence();
+    last = atomicAdd(arrive, 1u) == (u32)nb - 1;
   }
-}
-
-// One block: exclusive scan of partial[0..nb) in place, partial[nb] = total.
-template <class F>
-__global__ __launch_bounds__(PKT_BLOCK) void k_scan_partials(F f, i64* __restrict__ partial, int nb) {
-  if (!f.active()) return;
-  __shared__ i64 tmp[PKT_BLOCK / PKT_WAVE];
+  __syncthreads();
+  if (!last) return;
+  __threadfence();  // every block's chunk sum is visible
   i64 running = 0;
   for (int base = 0; base < nb; base += PKT_BLOCK) {
     const int i = base + threadIdx.x;
-    const i64 v = (i < nb) ? partial[i] : 0;
+    const i64 v = (i < nb) ? __hip_atomic_load(&partial[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
     i64 tot;
     const i64 ex = block_excl_scan_i64(v, tmp, &tot);
     if (i < nb) partial[i] = running + ex;
     running += tot;
   }
-  if (threadIdx.x == 0) partial[nb] = running;
+  if (threadIdx.x == 0) {
+    partial[nb] = running;
+    *arrive = 0;
+  }
 }
 
 template <class F>
@@ -56,7 +68,9 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_scan_down(F f, const i64* __restr
                                                         i64* __restrict__ out) {
   if (!f.active()) return;
   const i64 count = f.count();
-  const i64 chunk = (count + gridDim.x - 1) / gridDim.x;
+  const int nb = scan_nblocks(count);
+  if ((int)blockIdx.x >= nb) return;
+  const i64 chunk = (count + nb - 1) / nb;
   const i64 b0 = (i64)blockIdx.x * chunk;
   const i64 b1 = min(count, b0 + chunk);
   __shared__ i64 tmp[PKT_BLOCK / PKT_WAVE];
@@ -69,19 +83,16 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_scan_down(F f, const i64* __restr
     if (i < b1) out[i] = running + ex;
     running += tot;
   }
-  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[count] = partial[gridDim.x];
+  if ((int)blockIdx.x == nb - 1 && threadIdx.x == 0) out[count] = partial[nb];
 }
 
-// Launches the three passes on `stream`.  partial needs SCAN_BLOCKS + 1 entries.
 template <class F>
-static inline hipError_t scan_launch(const F& f, i64* partial, i64* out, hipStream_t stream) {
-  hipLaunchKernelGGL(k_scan_reduce<F>, dim3(SCAN_BLOCKS), dim3(PKT_BLOCK), 0, stream, f, partial);
-  hipLaunchKernelGGL(k_scan_partials<F>, dim3(1), dim3(PKT_BLOCK), 0, stream, f, partial, (int)SCAN_BLOCKS);
+static inline hipError_t scan_launch(const F& f, i64* partial, i64* out, u32* arrive, hipStream_t stream) {
+  hipLaunchKernelGGL(k_scan_reduce<F>, dim3(SCAN_BLOCKS), dim3(PKT_BLOCK), 0, stream, f, partial, arrive);
   hipLaunchKernelGGL(k_scan_down<F>, dim3(SCAN_BLOCKS), dim3(PKT_BLOCK), 0, stream, f, partial, out);
   return hipGetLastError();
 }
 
-// Functor over a plain array with a host-known count.
 template <class T>
 struct ArrayLen {
   const T* a;

@@ -9,11 +9,12 @@
 struct Ctl {
   i32 ncurr;       // edges in the current frontier F[sel]
   i32 nfound;      // edges appended to F[sel] by the level scan (atomic; becomes ncurr)
-  i32 nnext;       // edges appended to the next frontier F[sel ^ 1] (atomic)
+  i32 nnext;       // edges appended to the next frontier F[(sel + 1) % 3] (atomic)
+  i32 nprev;       // edges of the previous round's frontier F[(sel + 2) % 3]
   i32 nalive;      // entries of the alive list A[asel]
   i32 nalive_out;  // entries written to A[asel ^ 1] by the level scan (atomic)
   i32 level;       // support level l
-  i32 sel;         // frontier buffer in use
+  i32 sel;         // frontier buffer of the current round (0..2, rotating)
   i32 asel;        // alive-list buffer in use
   i32 min_above;   // min support among edges kept alive by the last scan (atomic min)
   i32 done;        // 1 once every edge is processed
@@ -38,6 +39,9 @@ struct Ctl {
   i32 force_choice;   // for TRUSS_VARIANT_FIXED
   float feat[8];      // features of the current frontier (TRUSS_NUM_FEATURES used)
   i32 scan_pending;   // level scan counted, not yet written (between its passes)
+  u32 scan_arrive;    // last-block-arrival counter of the device-wide scans (scan.h)
+  i32 chosen[TRUSS_NUM_CHOICES];  // rounds launched with each truss_choice
+  i32 round_done;     // a round kernel ran; k_decide ends the round
 };
 
 // Adjacency with edge ids: rows off[u]..off[u+1] of adj (sorted) and eid.
@@ -69,8 +73,8 @@ struct Work {
   i32* eid;         // [2m] edge id per adjacency slot
   int2* el;         // [m] endpoints (u < v)
   i32* S;           // [m] support
-  u8* state;        // [m] edge state
-  i32* F[2];        // [m] frontiers
+  u8* state;        // [m] edge state (ST_ALIVE, ST_PROC or a round tag)
+  i32* F[3];        // [m] frontiers: current, next, previous (rotating)
   i32* A[2];        // [m] alive lists
   i64* coff[2];     // [n+1] compacted offsets
   i32* cadj[2];     // [2m]

@@ -282,9 +282,10 @@ struct KeepLen {
 };
 
 __global__ __launch_bounds__(PKT_BLOCK) void k_keep_flags(Csr c, i64 slots, const u8* __restrict__ state,
-                                                         u8* __restrict__ flag) {
+                                                         const Ctl* __restrict__ ctl, u8* __restrict__ flag) {
+  const i32 r = ctl->sublevels;  // between rounds: the next round's index
   for (i64 j = (i64)blockIdx.x * PKT_BLOCK + threadIdx.x; j < slots; j += (i64)gridDim.x * PKT_BLOCK)
-    flag[j] = state[c.eid[j]] != ST_PROC;
+    flag[j] = !is_processed(state[c.eid[j]], r);
 }
 
 __global__ __launch_bounds__(PKT_BLOCK) void k_compact(i32 n, Csr c, i64 slots, const u8* __restrict__ flag,
@@ -349,7 +350,7 @@ size_t work_layout(i32 n, i64 two_m, bool off32, void* base, Work* w) {
   t.el = cv.take<int2>((size_t)m);
   t.S = cv.take<i32>((size_t)m);
   t.state = cv.take<u8>((size_t)m);
-  for (int k = 0; k < 2; ++k) t.F[k] = cv.take<i32>((size_t)m);
+  for (int k = 0; k < 3; ++k) t.F[k] = cv.take<i32>((size_t)m);
   for (int k = 0; k < 2; ++k) t.A[k] = cv.take<i32>((size_t)m);
   for (int k = 0; k < 2; ++k) {
     t.coff[k] = cv.take<i64>((size_t)n + 1);
@@ -405,10 +406,10 @@ truss_status build_edges(const Work& w, hipStream_t s) {
   const i32 n = w.n;
   hipLaunchKernelGGL(k_rowinfo, dim3(grid_for_h(n)), dim3(PKT_BLOCK), 0, s, n, w.off, w.adj, w.deg, w.locnt,
                      w.upcnt);
-  PKT_HIP(scan_launch(ArrayLen<i32>{(const i32*)w.upcnt, n}, w.partial, w.ebase, s));
+  PKT_HIP(scan_launch(ArrayLen<i32>{(const i32*)w.upcnt, n}, w.partial, w.ebase, &w.ctl->scan_arrive, s));
   hipLaunchKernelGGL(k_slots, dim3(grid_for_h(w.two_m)), dim3(PKT_BLOCK), 0, s, n, w.two_m, w.off, w.adj, w.deg,
                      w.locnt, w.ebase, w.eid, w.el, w.flag);
-  PKT_HIP(scan_launch(ArrayLen<u8>{w.flag, w.two_m}, w.partial, w.X, s));
+  PKT_HIP(scan_launch(ArrayLen<u8>{w.flag, w.two_m}, w.partial, w.X, &w.ctl->scan_arrive, s));
   hipLaunchKernelGGL(k_orient, dim3(grid_for_h(w.two_m)), dim3(PKT_BLOCK), 0, s, n, w.two_m, w.off, w.adj, w.eid,
                      w.flag, w.X, w.ooff, w.oadj, w.oeid);
   PKT_LAUNCH_CHECK();
@@ -453,8 +454,8 @@ truss_status compact(const Work& w, hipStream_t s) {
   PKT_HIP(hipMemcpyAsync(&slots, cur.off + w.n, sizeof(i64), hipMemcpyDeviceToHost, s));
   PKT_HIP(hipStreamSynchronize(s));
   hipLaunchKernelGGL(k_keep_flags, dim3(grid_for_h(slots)), dim3(PKT_BLOCK), 0, s, cur, slots,
-                     (const u8*)w.state, w.flag);
-  PKT_HIP(scan_launch(KeepLen{w.flag, slots}, w.partial, w.X, s));
+                     (const u8*)w.state, (const Ctl*)w.ctl, w.flag);
+  PKT_HIP(scan_launch(KeepLen{w.flag, slots}, w.partial, w.X, &w.ctl->scan_arrive, s));
   hipLaunchKernelGGL(k_compact, dim3(grid_for_h(slots)), dim3(PKT_BLOCK), 0, s, w.n, cur, slots,
                      (const u8*)w.flag, (const i64*)w.X, w.coff[dst - 1], w.cadj[dst - 1], w.ceid[dst - 1]);
   hipLaunchKernelGGL(k_after_compact, dim3(1), dim3(1), 0, s, w.ctl, dst, (i32)w.m);
@@ -492,6 +493,7 @@ __global__ void k_split_el(const int2* __restrict__ el, i64 m, i32* __restrict__
 namespace pkt {
 truss_status run_edge_list(const Work& w, i32* el_u, i32* el_v, hipStream_t s) {
   if (w.m == 0) return TRUSS_OK;
+  PKT_HIP(hipMemsetAsync(w.ctl, 0, sizeof(Ctl), s));  // zeroed counters for the scans
   truss_status st = build_edges(w, s);
   if (st) return st;
   hipLaunchKernelGGL(k_split_el, dim3(grid_for(w.m)), dim3(PKT_BLOCK), 0, s, (const int2*)w.el, w.m, el_u, el_v);

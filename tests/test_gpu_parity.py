@@ -93,6 +93,13 @@ def test_support_and_edge_list(gpu_lib, make):
     dict(force_choice="wide_narrow"),
     dict(force_choice="wide_gallop"),
     dict(single_round=True),
+    dict(device_loop="host"),
+    dict(device_loop="graph"),
+    dict(device_loop="device", steps_per_sync=1),
+    dict(device_loop="graph", steps_per_sync=3),
+    dict(device_loop="device", profile=True),
+    dict(device_loop="host", force_choice="wide_narrow"),
+    dict(device_loop="graph", force_choice="fused_narrow"),
 ])
 def test_medium_graphs(gpu_lib, make, opts):
     g = make()
@@ -172,6 +179,16 @@ def test_batched_full_config_sample(gpu_lib):
         g = b.graph(i)
         s = int(b.adj_off[i]) // 2
         assert np.array_equal(tau[s:s + g.m], oracle.truss(g)), i
+
+
+@pytest.mark.parametrize("mode", ["host", "device", "graph"])
+def test_loop_modes_full_size(gpu_lib, mode):
+    rec = _golden("rmat18")
+    g = gg.workload("rmat18", seed=rec["seed"])
+    say("case rmat18 loop", mode)
+    tau, st = gpu_lib.truss_decompose(g.offsets, g.adj, validate=False, device_loop=mode, return_stats=True)
+    assert sha(tau.cpu().numpy()) == rec["trussness_sha256"]
+    assert st["sublevels"] > 0 and sum(st["choice_count"]) > 0
 
 
 def _golden(name):
