@@ -80,7 +80,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat20", choices=sorted(WORKLOADS))
     ap.add_argument("--variant", default="auto")
-    ap.add_argument("--loop", default="host", choices=["host", "device", "graph"],
+    ap.add_argument("--loop", default="pipelined", choices=["host", "device", "graph", "pipelined"],
                     help="level-loop driver: host reads state per launch sequence; device/graph run gated steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,

@@ -112,15 +112,18 @@ typedef struct {
   int32_t variant;           /* truss_variant; default AUTO */
   int32_t device_loop;       /* 0 = host-driven: the host reads the loop state after every launch
                                 sequence; 1 = device-driven: batches of gated steps between host
-                                checks; 2 = as 1, the steps replayed from a captured hipGraph
-                                (default 0; a trace forces 0, profile turns 2 into 1) */
+                                checks; 2 = as 1, the steps replayed from a captured hipGraph;
+                                3 = pipelined host loop: a guessed next sequence is always in
+                                flight, the loop state is published to host-mapped memory and
+                                polled (default 3; a trace forces 0, profile turns 2 into 1) */
   int32_t validate;          /* 1 = check the input CSR before any other work (default 1) */
   int32_t owner_rule;        /* 0 = the lower edge id owns a two-frontier-edge triangle (the
                                 paper's rule, default); 1 = the higher id (the paper's stated
                                 alternative); for tests, the output does not change */
   int32_t compact;           /* 1 = periodically drop peeled edges from the working adjacency
                                 (default 1); 0 = intersect the full rows every time */
-  int32_t steps_per_sync;    /* device-driven loop: sub-level steps per host check (0 = auto) */
+  int32_t steps_per_sync;    /* device_loop 1, 2: steps per host check; 3: sequences in flight
+                                (at most 5); 0 = auto */
   const float* mlp_weights;  /* device: weights for TRUSS_VARIANT_LEARNED (truss_mlp_weights_floats
                                 floats), or NULL */
   truss_trace* trace;        /* host: per-sequence trace of the peeling loop, or NULL */

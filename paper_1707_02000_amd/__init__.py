@@ -24,7 +24,7 @@ LIB_PATH = os.path.join(_HERE, "libpkt.so")
 
 VARIANTS = {"auto": 0, "bsearch": 1, "merge": 2, "fixed": 3, "learned": 4}
 CHOICES = ["fused", "fused_narrow", "wide", "wide_narrow", "wide_gallop"]
-LOOP_MODES = {"host": 0, "device": 1, "graph": 2}  # truss_options.device_loop
+LOOP_MODES = {"host": 0, "device": 1, "graph": 2, "pipelined": 3}  # truss_options.device_loop
 
 
 def loop_mode(x) -> int:
@@ -183,7 +183,7 @@ def default_options() -> Options:
     return o
 
 
-def make_options(variant="auto", device_loop="host", validate=True, owner_rule=0, compact=True,
+def make_options(variant="auto", device_loop="pipelined", validate=True, owner_rule=0, compact=True,
                  steps_per_sync=0, mlp_weights=None, profile=False, force_choice=None,
                  single_round=False) -> Options:
     o = default_options()
@@ -263,7 +263,7 @@ class Workspace:
         return cls(n, two_m, buf, ptr, nb.value)
 
 
-def truss_decompose(offsets, adj, *, variant="auto", device_loop="host", validate=True, owner_rule=0,
+def truss_decompose(offsets, adj, *, variant="auto", device_loop="pipelined", validate=True, owner_rule=0,
                     compact=True, steps_per_sync=0, mlp_weights=None, stream=None, workspace=None,
                     out=None, return_stats=False, trace_capacity=0, profile=False, force_choice=None,
                     single_round=False):

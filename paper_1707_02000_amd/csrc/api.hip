@@ -34,8 +34,8 @@ static truss_status check_options(const truss_options* o) {
     set_error("owner_rule must be 0 or 1");
     return TRUSS_E_ARG;
   }
-  if (o->device_loop < 0 || o->device_loop > 2) {
-    set_error("device_loop must be 0 (host), 1 (device) or 2 (device, hipGraph)");
+  if (o->device_loop < 0 || o->device_loop > 3) {
+    set_error("device_loop must be 0 (host), 1 (device), 2 (device, hipGraph) or 3 (pipelined host)");
     return TRUSS_E_ARG;
   }
   if (o->steps_per_sync < 0) {
@@ -126,7 +126,7 @@ void truss_default_options(truss_options* opt) {
   if (!opt) return;
   memset(opt, 0, sizeof(*opt));
   opt->variant = TRUSS_VARIANT_AUTO;
-  opt->device_loop = 0;
+  opt->device_loop = 3;
   opt->validate = 1;
   opt->owner_rule = 0;
   opt->compact = 1;

@@ -18,6 +18,15 @@
 #define DECIDE_THREADS 512   // threads of the one-block kernel that picks a round's launch
 #define CHOICE_NONE (-1)     // Ctl::choice while no launch is picked for the current frontier
 
+// Loop state published by k_decide for the pipelined host loop (host-mapped,
+// LOOP_SNAP_SLOTS slots by sequence number).
+#define LOOP_SNAP_SLOTS 8
+struct LoopSnap {
+  i32 ncurr, choice, done, nalive, level, sublevels, processed, csr_edges;
+  i64 seq;
+  i64 pad[3];  // one 64-byte line per slot
+};
+
 // Everything a peeling kernel touches.
 struct PeelArgs {
   Ctl* ctl;

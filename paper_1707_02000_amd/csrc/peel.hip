@@ -28,6 +28,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <chrono>
 #include <vector>
 
 #include "mlp.h"
@@ -447,7 +448,7 @@ __device__ void lds_items(const PeelArgs& a, const Csr& c, const i32* curr, i32 
 
 // Snapshot of the control block shared through LDS by one block.
 struct CtlView {
-  i32 done, ncurr, level, sel, csel, nalive, asel, variant, choice, r, nprev;
+  i32 done, ncurr, level, sel, csel, nalive, asel, variant, choice, r, nprev, round_done;
 };
 
 __device__ __forceinline__ void load_view(const Ctl* ctl, CtlView* v) {
@@ -463,6 +464,7 @@ __device__ __forceinline__ void load_view(const Ctl* ctl, CtlView* v) {
     v->choice = ctl->choice;
     v->r = ctl->sublevels;
     v->nprev = ctl->nprev;
+    v->round_done = ctl->round_done;
   }
   __syncthreads();
 }
@@ -484,6 +486,22 @@ __device__ __forceinline__ bool arrive_last(Ctl* ctl, int* slast, int nblk) {
 }  // namespace
 
 // ---------------------------------------------------------------- single block
+
+// Loop state for the host, written to host-mapped memory: the fields first,
+// then the sequence number with a system-scope release, which the host polls.
+__device__ __forceinline__ void publish_snap(const Ctl* ctl, LoopSnap* snap, i64 seq) {
+  LoopSnap* slot = snap + (seq & (LOOP_SNAP_SLOTS - 1));
+  slot->ncurr = ctl->ncurr;
+  slot->choice = ctl->choice;
+  slot->done = ctl->done;
+  slot->nalive = ctl->nalive;
+  slot->level = ctl->level;
+  slot->sublevels = ctl->sublevels;
+  slot->processed = ctl->processed;
+  slot->csr_edges = ctl->csr_edges;
+  __threadfence_system();
+  __hip_atomic_store(&slot->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
 
 namespace {
 
@@ -796,22 +814,28 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_psl_bsearch(PeelArgs a, const i64
 // One block after a level scan or a round: ends the round the previous launch
 // ran (Ctl::round_done), goes on alone while the work stays small, then picks
 // the launch of the frontier left, if any (only when none is picked yet).
-__global__ __launch_bounds__(DECIDE_THREADS) void k_decide(PeelArgs a) {
+// With publish set, writes the loop state to the host-mapped slots Ctl::snap
+// under number seq (every path, also when there was nothing to do).  The slots'
+// address sits in device memory rather than in the arguments: a kernel whose
+// arguments point at host memory gets a system-scope release at its end.
+__global__ __launch_bounds__(DECIDE_THREADS) void k_decide(PeelArgs a, i64 seq, int publish) {
   Ctl* ctl = a.ctl;
   __shared__ AloneLds<DECIDE_THREADS> s;
-  load_view(ctl, &s.v);
-  if (s.v.done) return;
-  if (ctl->round_done) {
+  load_view(ctl, &s.v);  // block-uniform copy: thread 0 rewrites round_done below
+  bool go = !s.v.done && (s.v.round_done || s.v.choice == CHOICE_NONE);
+  if (go && s.v.round_done) {
     if (threadIdx.x == 0) {
       ctl_after_sublevel(ctl, s.v.ncurr, ctl->nnext, s.v.sel);
       ctl->round_done = 0;
       ctl->choice = CHOICE_NONE;
     }
     __syncthreads();
-  } else if (s.v.choice != CHOICE_NONE) {
-    return;
   }
-  leave<DECIDE_THREADS>(a, s);
+  if (go) leave<DECIDE_THREADS>(a, s);
+  if (publish) {
+    __syncthreads();
+    if (threadIdx.x == 0) publish_snap(ctl, ctl->snap, seq);
+  }
 }
 
 
@@ -837,7 +861,7 @@ struct Timer {
     on = enable;
     s = st;
     if (on)
-      for (int i = 0; i < 8; ++i) (void)hipEventCreate(&ev[i]);
+      for (int i = 0; i < 8; ++i) (void)hipEventCreateWithFlags(&ev[i], hipEventDisableSystemFence);
   }
   void mark() {
     if (on && k < 8) (void)hipEventRecord(ev[k++], s);
@@ -870,7 +894,8 @@ struct KernelClock {
   hipError_t mark(hipStream_t s) {
     if (used == ev.size()) {
       hipEvent_t e;
-      hipError_t r = hipEventCreate(&e);
+      // timing only: no system-scope fence (a cache writeback) at every record
+      hipError_t r = hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
       if (r != hipSuccess) return r;
       ev.push_back(e);
     }
@@ -924,15 +949,15 @@ static truss_status launch_round(const Work& w, const PeelArgs& a, const Ctl& hc
     const int G = scan_grid(hc.nalive);
     hipLaunchKernelGGL(k_scan_count, dim3(G), dim3(PKT_BLOCK), 0, s, a, w.partial, w.bmin);
     hipLaunchKernelGGL(k_scan_write, dim3(G), dim3(PKT_BLOCK), 0, s, a, (const i64*)w.partial);
-    hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a);
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a, (i64)0, 0);
   } else if (hc.choice == CHOICE_NONE) {
     *kind = 0;
-    hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a);
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a, (i64)0, 0);
   } else if (hc.choice == TRUSS_CHOICE_FUSED || hc.choice == TRUSS_CHOICE_FUSED_NARROW) {
     *kind = 1;
     const int blocks = hc.choice == TRUSS_CHOICE_FUSED ? FUSED_BLOCKS : FUSED_NARROW_BLOCKS;
     hipLaunchKernelGGL(k_psl_small, dim3(blocks), dim3(SMALL_THREADS), 0, s, a);
-    hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a);
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a, (i64)0, 0);
   } else {
     *kind = 2;
     // level 0: frontier edges lie in no triangle, nothing to intersect or scan
@@ -942,7 +967,7 @@ static truss_status launch_round(const Work& w, const PeelArgs& a, const Ctl& hc
     if (timed) PKT_HIP(prof->mark(s));
     hipLaunchKernelGGL(k_psl_bsearch, dim3(blocks), dim3(PKT_BLOCK), 0, s, a, (const i64*)w.X);
     if (timed) PKT_HIP(prof->mark(s));
-    hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a);
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a, (i64)0, 0);
   }
   PKT_LAUNCH_CHECK();
   return TRUSS_OK;
@@ -954,18 +979,125 @@ static truss_status launch_round(const Work& w, const PeelArgs& a, const Ctl& hc
 // reading anything.  Launches whose gate is closed return at once.  The first
 // k_decide ends the previous step's wide round.
 static truss_status enqueue_step(const Work& w, const PeelArgs& a, int G, hipStream_t s, KernelClock* prof) {
-  hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a);
+  hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a, (i64)0, 0);
   hipLaunchKernelGGL(k_scan_count, dim3(G), dim3(PKT_BLOCK), 0, s, a, w.partial, w.bmin);
   hipLaunchKernelGGL(k_scan_write, dim3(G), dim3(PKT_BLOCK), 0, s, a, (const i64*)w.partial);
-  hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a);
+  hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a, (i64)0, 0);
   hipLaunchKernelGGL(k_psl_small, dim3(FUSED_BLOCKS), dim3(SMALL_THREADS), 0, s, a);
-  hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a);
+  hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a, (i64)0, 0);
   PKT_HIP(scan_launch(WideLen{a}, w.partial, w.X, &w.ctl->scan_arrive, s));
   if (prof) PKT_HIP(prof->mark(s));
   hipLaunchKernelGGL(k_psl_bsearch, dim3(WIDE_BLOCKS), dim3(PKT_BLOCK), 0, s, a, (const i64*)w.X);
   if (prof) PKT_HIP(prof->mark(s));
   PKT_LAUNCH_CHECK();
   return TRUSS_OK;
+}
+
+// ---- pipelined host loop
+// The host keeps a few launch sequences in flight beyond the last loop state it
+// saw, guessed from that state.  Each sequence ends in k_decide, which
+// publishes the loop state to host-mapped memory; the host polls for it instead
+// of synchronizing the stream.  A wrong guess costs only its launches: every
+// kernel gates itself on the control block, and the data a kernel reads (the
+// work prefix of a wide round, the chunk offsets of a level scan) comes from the
+// launch just before it in the same sequence, under the same loop state.
+
+enum SeqKind { SEQ_SCAN = 0, SEQ_DECIDE = 1, SEQ_FUSED = 2, SEQ_WIDE = 3 };
+
+#define PIPE_DEPTH 2  // sequences in flight beyond the last state seen (default; measured best)
+#define PIPE_MAX 6
+static_assert(PIPE_MAX < LOOP_SNAP_SLOTS, "a slot must outlive the sequences in flight after it");
+
+inline int seq_kind(i32 ncurr, i32 choice) {
+  if (ncurr == 0) return SEQ_SCAN;
+  if (choice == CHOICE_NONE) return SEQ_DECIDE;
+  if (choice == TRUSS_CHOICE_FUSED || choice == TRUSS_CHOICE_FUSED_NARROW) return SEQ_FUSED;
+  return SEQ_WIDE;
+}
+
+// One sequence; the grids follow `choice` (its kind's full grid when it is not
+// of that kind) and the level-scan grid `nalive`.  The work scan of a wide round
+// is always launched (it gates itself on the level), so the round never reads a
+// stale prefix whatever state it meets.
+static truss_status enqueue_seq(const Work& w, const PeelArgs& a, int kind, int choice, i32 nalive, hipStream_t s,
+                                KernelClock* prof, i64 seq) {
+  if (kind == SEQ_SCAN) {
+    const int G = scan_grid(nalive);
+    hipLaunchKernelGGL(k_scan_count, dim3(G), dim3(PKT_BLOCK), 0, s, a, w.partial, w.bmin);
+    hipLaunchKernelGGL(k_scan_write, dim3(G), dim3(PKT_BLOCK), 0, s, a, (const i64*)w.partial);
+  } else if (kind == SEQ_FUSED) {
+    const int blocks = choice == TRUSS_CHOICE_FUSED_NARROW ? FUSED_NARROW_BLOCKS : FUSED_BLOCKS;
+    hipLaunchKernelGGL(k_psl_small, dim3(blocks), dim3(SMALL_THREADS), 0, s, a);
+  } else if (kind == SEQ_WIDE) {
+    PKT_HIP(scan_launch(WideLen{a}, w.partial, w.X, &w.ctl->scan_arrive, s));
+    const int blocks = choice == TRUSS_CHOICE_WIDE_NARROW ? WIDE_NARROW_BLOCKS : WIDE_BLOCKS;
+    if (prof) PKT_HIP(prof->mark(s));
+    hipLaunchKernelGGL(k_psl_bsearch, dim3(blocks), dim3(PKT_BLOCK), 0, s, a, (const i64*)w.X);
+    if (prof) PKT_HIP(prof->mark(s));
+  }
+  hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a, seq, 1);
+  PKT_LAUNCH_CHECK();
+  return TRUSS_OK;
+}
+
+thread_local LoopSnap* h_snap = nullptr;  // host-mapped, coherent
+thread_local LoopSnap* d_snap = nullptr;  // its device address
+thread_local i64 snap_seq = 0;            // sequence numbers, never reused in a thread
+
+truss_status snap_buffers() {
+  if (h_snap) return TRUSS_OK;
+  PKT_HIP(hipHostMalloc((void**)&h_snap, sizeof(LoopSnap) * LOOP_SNAP_SLOTS,
+                        hipHostMallocMapped | hipHostMallocCoherent));
+  memset(h_snap, 0, sizeof(LoopSnap) * LOOP_SNAP_SLOTS);
+  for (int i = 0; i < LOOP_SNAP_SLOTS; ++i) h_snap[i].seq = -1;
+  PKT_HIP(hipHostGetDevicePointer((void**)&d_snap, h_snap, 0));
+  return TRUSS_OK;
+}
+
+// Waits for the state published by sequence k.  Polls the slot; checks now and
+// then whether the stream has drained without it (an error, not a hang).
+truss_status wait_snap(i64 k, hipStream_t s, LoopSnap* out) {
+  volatile LoopSnap* slot = h_snap + (k & (LOOP_SNAP_SLOTS - 1));
+  auto t_check = std::chrono::steady_clock::now();
+  for (;;) {
+    if (__atomic_load_n(&h_snap[k & (LOOP_SNAP_SLOTS - 1)].seq, __ATOMIC_ACQUIRE) == k) {
+      out->ncurr = slot->ncurr;
+      out->choice = slot->choice;
+      out->done = slot->done;
+      out->nalive = slot->nalive;
+      out->level = slot->level;
+      out->sublevels = slot->sublevels;
+      out->processed = slot->processed;
+      out->csr_edges = slot->csr_edges;
+      out->seq = k;
+      return TRUSS_OK;
+    }
+    const auto now = std::chrono::steady_clock::now();
+    if (now - t_check > std::chrono::microseconds(200)) {
+      t_check = now;
+      const hipError_t q = hipStreamQuery(s);
+      if (q == hipSuccess) {
+        if (__atomic_load_n(&h_snap[k & (LOOP_SNAP_SLOTS - 1)].seq, __ATOMIC_ACQUIRE) == k) continue;
+        set_error("loop state %lld was not published", (long long)k);
+        return TRUSS_E_INTERNAL;
+      }
+      if (q != hipErrorNotReady) return hip_fail(q, "hipStreamQuery", __FILE__, __LINE__);
+    }
+  }
+}
+
+inline LoopSnap snap_of(const Ctl& c) {
+  LoopSnap x;
+  memset(&x, 0, sizeof(x));
+  x.ncurr = c.ncurr;
+  x.choice = c.choice;
+  x.done = c.done;
+  x.nalive = c.nalive;
+  x.level = c.level;
+  x.sublevels = c.sublevels;
+  x.processed = c.processed;
+  x.csr_edges = c.csr_edges;
+  return x;
 }
 
 #define GRAPH_STEPS 8  // steps per captured graph
@@ -1020,6 +1152,11 @@ truss_status run_single(const Work& w, const truss_options& opt, truss_stats* st
   init.force_choice = opt.force_choice;
   init.variant = opt.variant == TRUSS_VARIANT_MERGE ? TRUSS_VARIANT_MERGE : TRUSS_VARIANT_BSEARCH;
   init.choice = CHOICE_NONE;
+  if (opt.device_loop == 3 && !opt.trace) {
+    truss_status sb = snap_buffers();
+    if (sb) return sb;
+    init.snap = d_snap;
+  }
   PKT_HIP(hipMemcpyAsync(w.ctl, &init, sizeof(Ctl), hipMemcpyHostToDevice, s));
   if (opt.validate) {
     truss_status st = validate_input(w, s);
@@ -1048,8 +1185,8 @@ truss_status run_single(const Work& w, const truss_options& opt, truss_stats* st
   truss_trace* trace = opt.trace;
   hipEvent_t tev[2];
   if (trace) {
-    PKT_HIP(hipEventCreate(&tev[0]));
-    PKT_HIP(hipEventCreate(&tev[1]));
+    PKT_HIP(hipEventCreateWithFlags(&tev[0], hipEventDisableSystemFence));
+    PKT_HIP(hipEventCreateWithFlags(&tev[1], hipEventDisableSystemFence));
   }
   KernelClock clock;
   Ctl hc;
@@ -1066,7 +1203,80 @@ truss_status run_single(const Work& w, const truss_options& opt, truss_stats* st
     return read_ctl(w, &hc, s);
   };
   const int mode = trace ? 0 : opt.device_loop;  // a trace needs one sync per launch sequence
-  if (mode == 0) {
+  if (mode == 3) {
+    st = snap_buffers();
+    if (st) return st;
+    KernelClock* prof = opt.profile ? &clock : nullptr;
+    const int depth = opt.steps_per_sync > 0 ? (opt.steps_per_sync < PIPE_MAX ? opt.steps_per_sync : PIPE_MAX)
+                                             : PIPE_DEPTH;
+    struct Flight {
+      i64 seq;
+      int kind;
+    };
+    Flight fl[PIPE_MAX];
+    int nfl = 0;
+    LoopSnap cur = snap_of(hc);
+    int after_scan = SEQ_WIDE;  // kind of the round that followed the last level scan
+    auto guess_after = [&](int kind) { return kind == SEQ_SCAN ? after_scan : (kind == SEQ_DECIDE ? SEQ_WIDE : kind); };
+    // Tops the pipeline up to `depth` sequences.  The sequences in flight are
+    // replayed against the last state seen: one of the state's kind does its
+    // round (what follows is guessed: the same kind again, or after a level scan
+    // the kind that followed the last one); any other does nothing.  A sequence
+    // for a state known exactly gets that state's grids.
+    auto fill = [&]() -> truss_status {
+      int ks = seq_kind(cur.ncurr, cur.choice);
+      bool known = true;
+      for (int j = 0; j < nfl; ++j)
+        if (fl[j].kind == ks) {
+          ks = guess_after(ks);
+          known = false;
+        }
+      while (nfl < depth) {
+        const i64 q = ++snap_seq;
+        const int choice = known ? cur.choice : (ks == SEQ_FUSED ? TRUSS_CHOICE_FUSED : TRUSS_CHOICE_WIDE);
+        truss_status r = enqueue_seq(w, a, ks, choice, cur.nalive, s, prof, q);
+        if (r) return r;
+        fl[nfl++] = Flight{q, ks};
+        ks = guess_after(ks);
+        known = false;
+      }
+      return TRUSS_OK;
+    };
+    st = fill();
+    if (st) return st;
+    for (;;) {
+      const Flight f = fl[0];
+      for (int i = 1; i < nfl; ++i) fl[i - 1] = fl[i];
+      --nfl;
+      const LoopSnap prev = cur;
+      st = wait_snap(f.seq, s, &cur);
+      if (st) return st;
+      if (cur.done) break;
+      if (++guard > guard_max) {
+        set_error("level / sub-level count exceeded its bound");
+        return TRUSS_E_INTERNAL;
+      }
+      if (f.kind == SEQ_SCAN && seq_kind(prev.ncurr, prev.choice) == SEQ_SCAN) {
+        const int k = seq_kind(cur.ncurr, cur.choice);
+        if (k == SEQ_FUSED || k == SEQ_WIDE) after_scan = k;
+      }
+      if (opt.compact && (i64)(w.m - cur.processed) * 2 < (i64)cur.csr_edges) {
+        PKT_HIP(hipStreamSynchronize(s));  // lets the sequences in flight finish
+        nfl = 0;
+        st = read_ctl(w, &hc, s);
+        if (st) return st;
+        st = maybe_compact();
+        if (st) return st;
+        cur = snap_of(hc);
+        if (cur.done) break;
+      }
+      st = fill();
+      if (st) return st;
+    }
+    PKT_HIP(hipStreamSynchronize(s));
+    st = read_ctl(w, &hc, s);
+    if (st) return st;
+  } else if (mode == 0) {
     while (!hc.done) {
       if (++guard > guard_max) {
         set_error("level / sub-level count exceeded its bound");

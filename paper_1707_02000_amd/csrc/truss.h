@@ -42,6 +42,7 @@ struct Ctl {
   u32 scan_arrive;    // last-block-arrival counter of the device-wide scans (scan.h)
   i32 chosen[TRUSS_NUM_CHOICES];  // rounds launched with each truss_choice
   i32 round_done;     // a round kernel ran; k_decide ends the round
+  struct LoopSnap* snap;  // host-mapped loop-state slots (pipelined host loop) or null
 };
 
 // Adjacency with edge ids: rows off[u]..off[u+1] of adj (sorted) and eid.

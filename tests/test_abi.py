@@ -61,7 +61,7 @@ def test_default_options_and_struct_sizes(lib):
     import paper_1707_02000_amd as pkt
 
     o = pkt.default_options()
-    assert (o.variant, o.device_loop, o.validate, o.owner_rule, o.compact) == (0, 0, 1, 0, 1)
+    assert (o.variant, o.device_loop, o.validate, o.owner_rule, o.compact) == (0, 3, 1, 0, 1)
     assert ctypes.sizeof(pkt.Options) == 64
     assert ctypes.sizeof(pkt.Stats) == 136
     assert ctypes.sizeof(pkt.TraceRecord) == 72

@@ -100,6 +100,11 @@ def test_support_and_edge_list(gpu_lib, make):
     dict(device_loop="device", profile=True),
     dict(device_loop="host", force_choice="wide_narrow"),
     dict(device_loop="graph", force_choice="fused_narrow"),
+    dict(device_loop="pipelined"),
+    dict(device_loop="pipelined", force_choice="wide_narrow"),
+    dict(device_loop="pipelined", force_choice="fused_narrow"),
+    dict(device_loop="pipelined", variant="merge", profile=True),
+    dict(device_loop="pipelined", compact=False),
 ])
 def test_medium_graphs(gpu_lib, make, opts):
     g = make()
@@ -181,7 +186,7 @@ def test_batched_full_config_sample(gpu_lib):
         assert np.array_equal(tau[s:s + g.m], oracle.truss(g)), i
 
 
-@pytest.mark.parametrize("mode", ["host", "device", "graph"])
+@pytest.mark.parametrize("mode", ["host", "device", "graph", "pipelined"])
 def test_loop_modes_full_size(gpu_lib, mode):
     rec = _golden("rmat18")
     g = gg.workload("rmat18", seed=rec["seed"])
