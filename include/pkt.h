@@ -136,7 +136,9 @@ typedef struct {
   int32_t single_round;      /* 1 = every launch sequence runs exactly one frontier round (no
                                 continuation of tiny rounds inside the fused launch); for
                                 collecting per-round timing traces */
-  int32_t reserved[2];       /* must be zero */
+  int32_t* peel_round;       /* device, int32[m], or NULL: receives for every edge the index of the
+                                frontier round that processed it (a peeling order: rounds run in
+                                level order, so a lower trussness never gets a later round) */
 } truss_options;
 
 typedef struct {

@@ -11,6 +11,10 @@ Contents
   * ``definition`` -- the k-truss definition written out in pure Python for tiny
     graphs (repeated deletion of edges in fewer than k-2 triangles), support by set
     intersection, k-core numbers, and the local h-index iteration.
+  * ``certificate`` -- checks of a trussness array against the definition that hold at
+    any size, given a peeling order: every edge of trussness k lies in >= k-2
+    triangles of the edges of trussness >= k, and no edge had more than k-2 triangles
+    left when the order removed it; run on sampled edges at full scale.
   * ``psl_model`` -- a step-by-step model of the level-synchronous peeling
     (Algorithms 4 and 5 of the PKT section) whose threads interleave at random, to
     check the concurrency rules (lower-edge-id ownership, clamp and restore).
@@ -55,7 +59,7 @@ def _load():
     lib.oracle_edge_ids.restype = ctypes.c_int64
     lib.oracle_support.argtypes = [ctypes.c_int32, vp, vp, vp]
     lib.oracle_support.restype = ctypes.c_int64
-    lib.oracle_truss.argtypes = [ctypes.c_int32, vp, vp, vp, vp]
+    lib.oracle_truss.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp]
     lib.oracle_truss.restype = ctypes.c_int64
     _lib = lib
     return lib
@@ -102,15 +106,37 @@ def support(g) -> np.ndarray:
     return S[:m]
 
 
-def truss(g, with_support: bool = False):
-    """Trussness of every edge, canonical order (int32, >= 2); optionally the initial support."""
+def truss(g, with_support: bool = False, with_rank: bool = False):
+    """Trussness of every edge, canonical order (int32, >= 2).
+
+    with_support adds the initial support; with_rank adds the removal step of every
+    edge in the bucket peel (int64, a peeling order for ``certificate``).
+    """
     n, off, adj = _csr(g)
     m = int(off[-1]) // 2
     tau = np.zeros(max(m, 1), np.int32)
     S0 = np.zeros(max(m, 1), np.int32)
-    r = _load().oracle_truss(n, _ptr(off), _ptr(adj), _ptr(tau), _ptr(S0))
+    rank = np.zeros(max(m, 1), np.int64) if with_rank else None
+    r = _load().oracle_truss(n, _ptr(off), _ptr(adj), _ptr(tau), _ptr(S0), _ptr(rank) if with_rank else None)
     if r < 0:
         raise OracleInputError(f"oracle_truss failed ({r})")
+    out = (tau[:m],)
     if with_support:
-        return tau[:m], S0[:m]
-    return tau[:m]
+        out += (S0[:m],)
+    if with_rank:
+        out += (rank[:m],)
+    return out if len(out) > 1 else out[0]
+
+
+def edge_ids(g):
+    """(endpoints (m, 2) int32, edge id of every adjacency slot int32[2m]) in canonical order."""
+    n, off, adj = _csr(g)
+    two_m = int(off[-1])
+    m = two_m // 2
+    eu = np.zeros(max(m, 1), np.int32)
+    ev = np.zeros(max(m, 1), np.int32)
+    eid = np.zeros(max(two_m, 1), np.int32)
+    r = _load().oracle_edge_ids(n, _ptr(off), _ptr(adj), _ptr(eu), _ptr(ev), _ptr(eid))
+    if r < 0:
+        raise OracleInputError(f"oracle_edge_ids failed ({r})")
+    return np.stack([eu[:m], ev[:m]], axis=1), eid[:two_m]

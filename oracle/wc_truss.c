@@ -142,9 +142,12 @@ int64_t oracle_support(int32_t n, const int64_t* off, const int32_t* adj, int32_
 
 /*
  * Trussness of every edge in canonical edge order (tau[e] >= 2).  If S0 is
- * non-NULL it receives the initial support.  Returns m or a negative code.
+ * non-NULL it receives the initial support; if rank is non-NULL, rank[e] is the
+ * step at which edge e was removed (0 .. m-1, a peeling order).  Returns m or a
+ * negative code.
  */
-int64_t oracle_truss(int32_t n, const int64_t* off, const int32_t* adj, int32_t* tau, int32_t* S0) {
+int64_t oracle_truss(int32_t n, const int64_t* off, const int32_t* adj, int32_t* tau, int32_t* S0,
+                     int64_t* rank) {
   int rc = oracle_check_csr(n, off, adj);
   if (rc) return rc;
   int64_t two_m = off[n], m = two_m / 2;
@@ -221,6 +224,7 @@ int64_t oracle_truss(int32_t n, const int64_t* off, const int32_t* adj, int32_t*
     }
     gone[e] = 1;
     tau[e] = k + 2;
+    if (rank) rank[e] = i;
   }
   result = m;
 out:

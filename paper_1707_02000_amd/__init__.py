@@ -63,7 +63,7 @@ class Options(ctypes.Structure):
         ("batch_sequential", ctypes.c_int32),
         ("force_choice", ctypes.c_int32),
         ("single_round", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 2),
+        ("peel_round", ctypes.c_void_p),
     ]
 
 
@@ -266,12 +266,14 @@ class Workspace:
 def truss_decompose(offsets, adj, *, variant="auto", device_loop="pipelined", validate=True, owner_rule=0,
                     compact=True, steps_per_sync=0, mlp_weights=None, stream=None, workspace=None,
                     out=None, return_stats=False, trace_capacity=0, profile=False, force_choice=None,
-                    single_round=False):
+                    single_round=False, return_rounds=False):
     """Trussness (int32, >= 2) of every edge of a simple undirected CSR graph, on the GPU.
 
     offsets: int64 (or int32) [n+1]; adj: int32 [2m]; numpy arrays (copied to the GPU) or
     CUDA tensors.  Returns a CUDA int32 tensor [m] (and a stats dict if return_stats; with
     trace_capacity > 0 the stats dict also holds the per-sequence trace of the peeling loop).
+    With return_rounds, also the frontier round that processed every edge (int32 [m], a
+    peeling order), right after the trussness.
     """
     torch = _torch()
     lib = load()
@@ -291,6 +293,10 @@ def truss_decompose(offsets, adj, *, variant="auto", device_loop="pipelined", va
         _buf, wptr, nb = workspace.buf, workspace.ptr, workspace.nbytes
     if out is None:
         out = torch.empty(max(m, 1), dtype=torch.int32, device="cuda")
+    rounds = None
+    if return_rounds:
+        rounds = torch.full((max(m, 1),), -1, dtype=torch.int32, device="cuda")
+        opt.peel_round = ctypes.c_void_p(rounds.data_ptr())
     st = Stats()
     trace = None
     if trace_capacity > 0:
@@ -305,7 +311,8 @@ def truss_decompose(offsets, adj, *, variant="auto", device_loop="pipelined", va
     sd = st.as_dict()
     if trace is not None:
         sd["trace"] = [recs[i].as_dict() for i in range(trace.count)]
-    return (res, sd) if return_stats else res
+    ret = (res,) + ((rounds[:m],) if return_rounds else ()) + ((sd,) if return_stats else ())
+    return ret if len(ret) > 1 else res
 
 
 def truss_support(offsets, adj, *, stream=None):

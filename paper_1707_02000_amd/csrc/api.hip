@@ -46,11 +46,6 @@ static truss_status check_options(const truss_options* o) {
     set_error("force_choice must be a truss_choice");
     return TRUSS_E_ARG;
   }
-  for (int i = 0; i < 2; ++i)
-    if (o->reserved[i] != 0) {
-      set_error("reserved option fields must be zero");
-      return TRUSS_E_ARG;
-    }
   if (o->variant == TRUSS_VARIANT_LEARNED && o->mlp_weights == nullptr) {
     set_error("TRUSS_VARIANT_LEARNED needs mlp_weights");
     return TRUSS_E_ARG;

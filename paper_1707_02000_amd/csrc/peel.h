@@ -37,6 +37,7 @@ struct PeelArgs {
   CsrSet csr;
   i32* S;
   u8* state;
+  i32* order;  // truss_options::peel_round, or NULL
   int owner_higher;
   int single_round;
   const float* mlp;  // cost-model weights (TRUSS_VARIANT_LEARNED) or NULL

@@ -50,7 +50,8 @@ namespace {
 // it stays <= l for the level, so a stale read can only cause a decrement that
 // is then undone.  The next-frontier tag written here reads as "not current"
 // and "not processed" to every other thread of the round, as it should.
-__device__ __forceinline__ i32 psl_rule(i32 x, i32 y, i32 e1, i32 l, i32 r, i32* S, u8* state, int owner_higher) {
+__device__ __forceinline__ i32 psl_rule(i32 x, i32 y, i32 e1, i32 l, i32 r, i32* S, u8* state, i32* order,
+                                        int owner_higher) {
   if (atomic_load_relaxed(&S[x]) <= l) return -1;
   const bool y_curr = state[y] == round_tag(r);
   const bool mine = !y_curr || (owner_higher ? (e1 > y) : (e1 < y));
@@ -58,6 +59,7 @@ __device__ __forceinline__ i32 psl_rule(i32 x, i32 y, i32 e1, i32 l, i32 r, i32*
   const i32 a = atomicSub(&S[x], 1);
   if (a == l + 1) {
     state[x] = round_tag(r + 1);
+    if (order) order[x] = r + 1;
     return x;
   }
   if (a <= l) atomicAdd(&S[x], 1);
@@ -249,8 +251,8 @@ __device__ __forceinline__ void psl_item(const PeelArgs& a, const Csr& c, i32 e1
     const i32 eo = c.eid[p];
     ++p;
     if (is_processed(a.state[eo], rd)) continue;
-    const i32 y[2] = {psl_rule(es, eo, e1, l, rd, a.S, a.state, a.owner_higher),
-                      psl_rule(eo, es, e1, l, rd, a.S, a.state, a.owner_higher)};
+    const i32 y[2] = {psl_rule(es, eo, e1, l, rd, a.S, a.state, a.order, a.owner_higher),
+                      psl_rule(eo, es, e1, l, rd, a.S, a.state, a.order, a.owner_higher)};
     for (int q = 0; q < 2; ++q) {
       if (y[q] < 0) continue;
       if (x0 < 0)
@@ -388,6 +390,7 @@ __device__ void scan_tiles(const PeelArgs& a, i32 l, i32 r, i32 na, const i32* _
       if ((tk >> k) & 1u) {
         curr[sbase[0] + pt[k]] = ev[k];
         a.state[ev[k]] = round_tag(r);
+        if (a.order) a.order[ev[k]] = r;
       } else if ((kp >> k) & 1u) {
         Aout[sbase[1] + pk[k]] = ev[k];
       }
@@ -709,6 +712,7 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_scan_write(PeelArgs a, const i64*
       if ((tk >> k) & 1u) {
         curr[bt + pt[k]] = ev[k];
         a.state[ev[k]] = round_tag(r);
+        if (a.order) a.order[ev[k]] = r;
       } else if ((kp >> k) & 1u) {
         Aout[bk + pk[k]] = ev[k];
       }
@@ -926,6 +930,7 @@ PeelArgs peel_args(const Work& w, const truss_options& opt) {
   a.csr = csr_set(w);
   a.S = w.S;
   a.state = w.state;
+  a.order = opt.peel_round;
   a.owner_higher = opt.owner_rule == 1;
   a.single_round = opt.single_round != 0;
   a.mlp = opt.mlp_weights;

@@ -102,7 +102,7 @@ def test_bad_arguments_rejected_before_device_work(lib):
     code = lib.truss_decompose(4, None, None, None, None, 0, ctypes.byref(o), None, None)
     assert code == 1
     o = pkt.default_options()
-    o.reserved[1] = 1
+    o.device_loop = 7
     code = lib.truss_decompose(4, None, None, None, None, 0, ctypes.byref(o), None, None)
     assert code == 1
 

@@ -15,6 +15,7 @@ import pytest
 
 import graphgen as gg
 import oracle
+from oracle import certificate
 from oracle import definition as D
 
 pytestmark = pytest.mark.gpu
@@ -215,3 +216,57 @@ def test_full_size_against_stored_oracle(gpu_lib, name):
     assert np.bincount(tau).tolist() == rec["histogram"]
     assert sha(tau) == rec["trussness_sha256"]
     assert st["triangles"] == rec["triangles"]
+
+
+# ---- peeling-order certificates (oracle/certificate.py): exact at any size
+
+@pytest.mark.parametrize("make", [
+    lambda: gg.rmat(13, 16, seed=5),
+    lambda: gg.chunglu(1 << 12, 2.1, 3.0e4, draws=27_000, ncliques=4, cmin=10, cmax=40, seed=6),
+])
+@pytest.mark.parametrize("mode", ["pipelined", "host"])
+def test_rounds_are_a_peeling_certificate(gpu_lib, make, mode):
+    g = make()
+    say("case", g.name, mode)
+    tau, rounds = gpu_lib.truss_decompose(g.offsets, g.adj, device_loop=mode, return_rounds=True)
+    tau, rounds = tau.cpu().numpy(), rounds.cpu().numpy()
+    assert np.array_equal(tau, oracle.truss(g))
+    res = certificate.verify(g, tau, rounds)
+    assert res["ok"], (res["monotone"], res["lower_bound_fails"][:5], res["upper_bound_fails"][:5])
+
+
+def _sampled_support_ok(g, S, edges):
+    cert = certificate.Certificate(g)
+    return all(len(cert.partners(int(e))[0]) == int(S[e]) for e in edges)
+
+
+@pytest.mark.parametrize("name", ["rmat24", "chunglu23"])
+def test_full_size_certificate(gpu_lib, name):
+    """Full-size inputs the serial oracle cannot finish in a test: the trussness is checked
+    against the definition through the peeling-order certificate on a stratified sample
+    (every trussness value), the support on a sample, and two loop drivers agree."""
+    import time
+
+    import torch
+
+    t0 = time.time()
+    g = gg.workload(name, seed=1)
+    say("case", name, "n", g.n, "m", g.m, "generated in", round(time.time() - t0, 1), "s")
+    off, adj = torch.from_numpy(g.offsets).cuda(), torch.from_numpy(g.adj).cuda()
+    t0 = time.time()
+    tau, rounds, st = gpu_lib.truss_decompose(off, adj, validate=True, return_rounds=True, return_stats=True)
+    tau, rounds = tau.cpu().numpy(), rounds.cpu().numpy()
+    say("decomposed in", round(time.time() - t0, 2), "s; t_max", st["t_max"], "levels", st["levels"],
+        "rounds", st["sublevels"])
+    assert int(tau.min()) >= 2 and int(tau.max()) == st["t_max"]
+    assert int(rounds.min()) >= 0 and st["sublevels"] == int(rounds.max()) + 1
+    assert certificate.monotone_order(tau, rounds)
+    edges = certificate.sample_edges(tau, n_uniform=20_000, per_value=20)
+    res = certificate.Certificate(g).check(tau, rounds, edges)
+    say("certificate on", len(edges), "edges:", len(res["lower_bound_fails"]), len(res["upper_bound_fails"]), "fails")
+    assert not res["lower_bound_fails"] and not res["upper_bound_fails"]
+    S = gpu_lib.truss_support(off, adj).cpu().numpy()
+    assert int(S.sum()) == 3 * st["triangles"]
+    assert _sampled_support_ok(g, S, edges[:5000])
+    tau2 = gpu_lib.truss_decompose(off, adj, validate=False, device_loop="host").cpu().numpy()
+    assert np.array_equal(tau, tau2)

@@ -34,7 +34,7 @@ def _pins_pass(lib):
         adj = np.ascontiguousarray(g.adj if len(g.adj) else np.zeros(1, np.int32), np.int32)
         tau = np.zeros(max(m, 1), np.int32)
         r = lib.oracle_truss(g.n, off.ctypes.data_as(ctypes.c_void_p), adj.ctypes.data_as(ctypes.c_void_p),
-                             tau.ctypes.data_as(ctypes.c_void_p), None)
+                             tau.ctypes.data_as(ctypes.c_void_p), None, None)
         return None if r < 0 else tau[:m]
 
     for n in range(3, 9):  # closed form: K_n -> n
@@ -60,7 +60,7 @@ def _compile(src_text, tmp_path, name):
     c.write_text(src_text)
     subprocess.check_call(["gcc", "-O1", "-fPIC", "-shared", "-w", "-o", str(so), str(c)])
     lib = ctypes.CDLL(str(so))
-    lib.oracle_truss.argtypes = [ctypes.c_int32] + [ctypes.c_void_p] * 4
+    lib.oracle_truss.argtypes = [ctypes.c_int32] + [ctypes.c_void_p] * 5
     lib.oracle_truss.restype = ctypes.c_int64
     return lib
 
@@ -74,7 +74,7 @@ def _child(path, q):
 
     faulthandler.disable()  # a crashing mutant is an expected outcome here
     lib = ctypes.CDLL(path)
-    lib.oracle_truss.argtypes = [ctypes.c_int32] + [ctypes.c_void_p] * 4
+    lib.oracle_truss.argtypes = [ctypes.c_int32] + [ctypes.c_void_p] * 5
     lib.oracle_truss.restype = ctypes.c_int64
     q.put(_pins_pass(lib))
 
