@@ -48,12 +48,14 @@ namespace {
 // Returns x if it joined the next frontier, else -1.  The plain pre-read of S
 // may be stale: while S[x] > l every older value is > l too, and once S[x] <= l
 // it stays <= l for the level, so a stale read can only cause a decrement that
-// is then undone.  The next-frontier tag written here reads as "not current"
-// and "not processed" to every other thread of the round, as it should.
-__device__ __forceinline__ i32 psl_rule(i32 x, i32 y, i32 e1, i32 l, i32 r, i32* S, u8* state, i32* order,
-                                        int owner_higher) {
+// is then undone.  y_curr comes from the caller's earlier read of y's state:
+// during a round a state can only change between values that are not the
+// round's tag (alive -> next, previous round -> processed), so that read
+// answers "is y current" for the whole round.  The next-frontier tag written
+// here reads as "not current" and "not processed" to every other thread.
+__device__ __forceinline__ i32 psl_rule(i32 x, bool y_curr, i32 y, i32 e1, i32 l, i32 r, i32* S, u8* state,
+                                        i32* order, int owner_higher) {
   if (atomic_load_relaxed(&S[x]) <= l) return -1;
-  const bool y_curr = state[y] == round_tag(r);
   const bool mine = !y_curr || (owner_higher ? (e1 > y) : (e1 < y));
   if (!mine) return -1;
   const i32 a = atomicSub(&S[x], 1);
@@ -241,18 +243,21 @@ __device__ __forceinline__ void psl_item(const PeelArgs& a, const Csr& c, i32 e1
   const i64 k = chunk_of(variant);
   const i64 j0 = r.sb + t * k, j1 = min(r.sb + r.slen, j0 + k);
   i64 p = r.lb;
+  const u8 tcur = round_tag(rd);
   for (i64 j = j0; j < j1; ++j) {
     const i32 es = c.eid[j];
-    if (is_processed(a.state[es], rd)) continue;
+    const u8 ss = a.state[es];
+    if (is_processed(ss, rd)) continue;
     const i32 w = c.adj[j];
     p = (j == j0) ? lower_bound_dev(c.adj, p, r.le, w) : gallop(c.adj, p, r.le, w);
     if (p == r.le) break;
     if (c.adj[p] != w) continue;
     const i32 eo = c.eid[p];
     ++p;
-    if (is_processed(a.state[eo], rd)) continue;
-    const i32 y[2] = {psl_rule(es, eo, e1, l, rd, a.S, a.state, a.order, a.owner_higher),
-                      psl_rule(eo, es, e1, l, rd, a.S, a.state, a.order, a.owner_higher)};
+    const u8 so = a.state[eo];
+    if (is_processed(so, rd)) continue;
+    const i32 y[2] = {psl_rule(es, so == tcur, eo, e1, l, rd, a.S, a.state, a.order, a.owner_higher),
+                      psl_rule(eo, ss == tcur, es, e1, l, rd, a.S, a.state, a.order, a.owner_higher)};
     for (int q = 0; q < 2; ++q) {
       if (y[q] < 0) continue;
       if (x0 < 0)
@@ -768,17 +773,95 @@ struct WideLen {
   }
 };
 
+// Tile of the wide round whose items all belong to one frontier edge (search
+// variant: one shorter-row entry per item).  The block stages NSAMP evenly
+// spaced entries of the longer row in LDS (the whole row when it is at most
+// NSAMP long, as for most of the work on skewed graphs); a lane finds the bracket of its entry among the samples in LDS and
+// binary-searches only that bracket, at most `step` contiguous entries, in
+// memory.  Consecutive tiles of one edge keep the staged samples.
+#define NSAMP 4096
+
+struct TileEdge {
+  i64 i0;            // frontier index of the staged edge (-1: none)
+  i64 sb, lb, step;  // shorter-row start, longer-row start, sample spacing
+  i32 e1, L, ns;     // edge id, longer-row length, samples staged
+};
+
+__device__ void tile_one_edge(const PeelArgs& a, const Csr& c, const i32* curr, const i64* __restrict__ P, i64 i0,
+                              i64 base, i64 total, i32 l, i32 r, i32* next, TileEdge& te, i32* samp) {
+  if (te.i0 != i0) {  // block-uniform
+    __syncthreads();  // the previous tile's lanes are done with samp
+    if (threadIdx.x == 0) {
+      const i32 e1 = curr[i0];
+      const Rows rw = rows_of(c, a.el[e1]);
+      const i64 L = rw.le - rw.lb;
+      const i64 step = L > NSAMP ? (L + NSAMP - 1) / NSAMP : 1;
+      te.i0 = i0;
+      te.e1 = e1;
+      te.sb = rw.sb;
+      te.lb = rw.lb;
+      te.L = (i32)L;
+      te.step = step;
+      te.ns = (i32)((L + step - 1) / step);
+    }
+    __syncthreads();
+    for (i32 k = threadIdx.x; k < te.ns; k += PKT_BLOCK) samp[k] = c.adj[te.lb + (i64)k * te.step];
+    __syncthreads();
+  }
+  const i64 g = base + threadIdx.x;
+  i32 x0 = -1, x1 = -1;
+  if (g < total) {
+    // The entry's edge id and state are read only once a triangle is found: most
+    // entries find none, and the search here costs no memory access past the
+    // entry itself (LDS, or one line of the longer row).
+    const i64 j = te.sb + (g - P[i0]);
+    const i32 w = c.adj[j];
+    i32 lo = 0, hi = te.ns;  // first sample >= w
+    while (lo < hi) {
+      const i32 mid = (lo + hi) >> 1;
+      if (samp[mid] < w)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    i64 p = -1;
+    if (lo < te.ns && samp[lo] == w) {
+      p = te.lb + (i64)lo * te.step;
+    } else if (te.step > 1) {  // between samples lo - 1 and lo: positions ((lo-1)*step, lo*step)
+      const i64 q0 = lo > 0 ? (i64)(lo - 1) * te.step + 1 : 0;
+      const i64 q1 = min((i64)lo * te.step, (i64)te.L);
+      const i64 q = lower_bound_dev(c.adj, te.lb + q0, te.lb + q1, w);
+      if (q < te.lb + q1 && c.adj[q] == w) p = q;
+    }
+    if (p >= 0) {
+      const i32 es = c.eid[j], eo = c.eid[p];
+      const u8 ss = a.state[es], so = a.state[eo];
+      if (!is_processed(ss, r) && !is_processed(so, r)) {
+        const u8 tcur = round_tag(r);
+        x0 = psl_rule(es, so == tcur, eo, te.e1, l, r, a.S, a.state, a.order, a.owner_higher);
+        x1 = psl_rule(eo, ss == tcur, es, te.e1, l, r, a.S, a.state, a.order, a.owner_higher);
+      }
+    }
+  }
+  append_next(x0, x1, next, &a.ctl->nnext);
+}
+
 // Wide round: one thread per intersection item over the whole grid, items
 // located through the device-wide work prefix P (not read at level 0, where
-// there are no items); k_decide follows and ends the round.
-// TRUSS_CHOICE_WIDE_NARROW uses the first WIDE_NARROW_BLOCKS blocks.  Kept
-// lean: its register count sets the occupancy of the item loop, and no block
-// fences or counts arrivals (a device-scope fence per block costs more than the
-// kernel boundary that orders the round's end).
+// there are no items); k_decide follows and ends the round.  Each block takes a
+// contiguous range of tiles of PKT_BLOCK items; a tile inside one edge's items
+// takes the staged-sample path (tile_one_edge), any other tile locates every
+// item's edge and searches the longer row directly.  TRUSS_CHOICE_WIDE_NARROW
+// uses the first WIDE_NARROW_BLOCKS blocks.  Kept lean: its register count sets
+// the occupancy of the item loop, and no block fences or counts arrivals (a
+// device-scope fence per block costs more than the kernel boundary that orders
+// the round's end).
 __global__ __launch_bounds__(PKT_BLOCK) void k_psl_bsearch(PeelArgs a, const i64* __restrict__ P) {
   Ctl* ctl = a.ctl;
   __shared__ CtlView v;
   __shared__ i64 sp[2];
+  __shared__ TileEdge te;
+  __shared__ i32 samp[NSAMP];
   load_view(ctl, &v);
   if (v.done || v.ncurr == 0 || !is_wide(v.choice)) return;
   const int nblk = v.choice == TRUSS_CHOICE_WIDE_NARROW ? min((int)gridDim.x, WIDE_NARROW_BLOCKS) : gridDim.x;
@@ -799,18 +882,28 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_psl_bsearch(PeelArgs a, const i64
       ctl->wide_launches += 1;
     }
   }
-  for (i64 base = (i64)blockIdx.x * PKT_BLOCK; base < total; base += (i64)nblk * PKT_BLOCK) {
+  if (threadIdx.x == 0) te.i0 = -1;
+  const i64 tiles = (total + PKT_BLOCK - 1) / PKT_BLOCK;
+  const i64 per = (tiles + nblk - 1) / nblk;
+  const i64 t_end = min(tiles, ((i64)blockIdx.x + 1) * per);
+  for (i64 tile = (i64)blockIdx.x * per; tile < t_end; ++tile) {
+    const i64 base = tile * PKT_BLOCK;
     if (threadIdx.x == 0) sp[0] = upper_bound_dev(P, (i64)0, npairs + 1, base) - 1;
     if (threadIdx.x == PKT_WAVE)
       sp[1] = upper_bound_dev(P, (i64)0, npairs + 1, min(base + PKT_BLOCK, total) - 1) - 1;
     __syncthreads();
-    const i64 g = base + threadIdx.x;
-    i32 x0 = -1, x1 = -1;
-    if (g < total) {
-      const i64 i = upper_bound_dev(P, sp[0], sp[1] + 1, g) - 1;
-      psl_item(a, c, curr[i], g - P[i], l, r, variant, x0, x1, next, &ctl->nnext);
+    const i64 s0 = sp[0], s1 = sp[1];
+    if (s0 == s1 && variant == TRUSS_VARIANT_BSEARCH) {
+      tile_one_edge(a, c, curr, P, s0, base, total, l, r, next, te, samp);
+    } else {
+      const i64 g = base + threadIdx.x;
+      i32 x0 = -1, x1 = -1;
+      if (g < total) {
+        const i64 i = upper_bound_dev(P, s0, s1 + 1, g) - 1;
+        psl_item(a, c, curr[i], g - P[i], l, r, variant, x0, x1, next, &ctl->nnext);
+      }
+      append_next(x0, x1, next, &ctl->nnext);
     }
-    append_next(x0, x1, next, &ctl->nnext);
     __syncthreads();
   }
 }
