@@ -73,6 +73,65 @@ def cpu_baseline(sample_name="rmat16"):
                       f"(m={g.m}); one full serial decomposition, {dt:.1f} s"}
 
 
+def _timed(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def extras(pkt, torch, gg, off20, adj20, m20, ms20, steps):
+    """The other parts of the metric: learned dispatch vs the plain heuristic (R-MAT s20
+    and s24), R-MAT s24 itself, and batched (one union level loop) vs one graph after
+    another.  Each timed like the main line (inputs resident, one warm-up)."""
+    from paper_1707_02000_amd import tuner
+
+    out = {}
+    W = tuner.load_weights()
+    t = _timed(lambda: pkt.truss_decompose(off20, adj20, validate=False, variant="learned", mlp_weights=W),
+               steps, 1, torch)
+    out["learned_rmat20"] = {"value": m20 / t, "ms_per_step": t * 1e3, "vs_plain": ms20 / (t * 1e3)}
+    print(f"bench: learned rmat20 {t * 1e3:.1f} ms", file=sys.stderr, flush=True)
+
+    g = gg.workload("rmat24", seed=1)
+    off = torch.from_numpy(g.offsets).cuda()
+    adj = torch.from_numpy(g.adj).cuda()
+    ws = pkt.Workspace.for_graph(g.n, len(g.adj))
+    o = torch.empty(g.m, dtype=torch.int32, device="cuda")
+    ref, st = pkt.truss_decompose(off, adj, validate=True, workspace=ws, out=o, return_stats=True)
+    ref = ref.clone()
+    tp = _timed(lambda: pkt.truss_decompose(off, adj, validate=False, workspace=ws, out=o), 2, 0, torch)
+    tl = _timed(lambda: pkt.truss_decompose(off, adj, validate=False, workspace=ws, out=o, variant="learned",
+                                            mlp_weights=W), 2, 0, torch)
+    same = bool(torch.equal(o, ref))
+    out["rmat24"] = {"m": g.m, "value": g.m / tp, "ms_per_step": tp * 1e3, "t_max": st["t_max"],
+                     "levels": st["levels"], "sublevels": st["sublevels"],
+                     "learned_value": g.m / tl, "learned_vs_plain": tp / tl, "learned_bit_identical": same}
+    print(f"bench: rmat24 plain {tp * 1e3:.0f} ms learned {tl * 1e3:.0f} ms", file=sys.stderr, flush=True)
+    del off, adj, ws, o, ref
+    torch.cuda.empty_cache()
+
+    b = gg.workload("batch4096", seed=1)
+    args_b = [torch.from_numpy(x).cuda() for x in (b.vtx_off, b.adj_off, b.offsets, b.adj)]
+    tb = _timed(lambda: pkt.truss_decompose_batched(*args_b, validate=False), 2, 1, torch)
+    G = 256  # the sequential comparison on the first graphs (one after another is slow)
+    sub = [torch.from_numpy(x).cuda() for x in
+           (b.vtx_off[:G + 1], b.adj_off[:G + 1], b.offsets[:int(b.vtx_off[G])], b.adj[:int(b.adj_off[G])])]
+    m_sub = int(b.adj_off[G]) // 2
+    tu = _timed(lambda: pkt.truss_decompose_batched(*sub, validate=False), 2, 1, torch)
+    tsq = _timed(lambda: pkt.truss_decompose_batched(*sub, validate=False, sequential=True), 1, 1, torch)
+    out["batch4096"] = {"graphs": b.num_graphs, "m": b.total_m, "value": b.total_m / tb, "ms_per_step": tb * 1e3,
+                        "first_256": {"m": m_sub, "union_value": m_sub / tu, "sequential_value": m_sub / tsq,
+                                      "union_vs_sequential": tsq / tu}}
+    print(f"bench: batch4096 {tb * 1e3:.0f} ms; first 256 union {tu * 1e3:.1f} ms sequential {tsq * 1e3:.1f} ms",
+          file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +142,8 @@ def main():
     ap.add_argument("--loop", default="pipelined", choices=["host", "device", "graph", "pipelined"],
                     help="level-loop driver: host reads state per launch sequence; device/graph run gated steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the learned / R-MAT s24 / batched comparison fields")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (5 times), to scale "
                          "the FETCH_SIZE / WRITE_SIZE hardware counters")
@@ -189,6 +250,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": None,
     }
+    if not args.no_extras and args.workload == "rmat20":
+        line["extras"] = extras(pkt, torch, gg, off, adj, g.m, ms, args.steps)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)
