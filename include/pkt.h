@@ -77,8 +77,10 @@ typedef enum {
   TRUSS_VARIANT_MERGE = 2,   /* galloping search in every round (FUSED rounds gallop too) */
   TRUSS_VARIANT_FIXED = 3,   /* every round uses truss_options.force_choice (where valid) */
   TRUSS_VARIANT_LEARNED = 4  /* the MLP cost model (truss_options.mlp_weights) predicts the time
-                                of every valid choice from the frontier's features and the
-                                cheapest is launched; the heuristic is its fallback */
+                                of every valid choice from the frontier's features (frontiers of
+                                more than 256 edges); the cheapest is launched when it is predicted
+                                at least 25 % faster than the heuristic's launch, which stands
+                                otherwise and for smaller frontiers */
 } truss_variant;
 
 /* Features of a frontier, in the order the cost model and the trace use them:
@@ -272,9 +274,10 @@ truss_status truss_mlp_train(const float* X, const float* T, const float* M, int
                              float lr, float* loss_history, void* workspace, size_t workspace_bytes, void* stream);
 
 /* The peeling loop's decision for n frontiers: choice[i] = the valid choice of
- * least predicted time (fused choices are valid up to 2048 frontier edges, ncurr
- * gives each frontier's size); Y (or NULL) receives the predictions.  Uses the same
- * device inference routine as the loop. */
+ * least predicted time if it beats the heuristic's launch by 25 % (log2 margin
+ * 0.32), else the heuristic's launch (fused choices are valid up to 2048 frontier
+ * edges, ncurr gives each frontier's size); Y (or NULL) receives the predictions.
+ * Uses the same device inference and decision routines as the loop. */
 truss_status truss_mlp_choose(const float* X, const int32_t* ncurr, int32_t n, const float* weights, int32_t* choice,
                               float* Y, void* stream);
 

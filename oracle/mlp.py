@@ -85,11 +85,24 @@ def gradient(w, X, T, M, k):
     return out
 
 
-def choose(w, X, ncurr, k, fused=(0, 1), fused_limit=2048):
-    """The decision rule: the valid choice with the least predicted time."""
+MARGIN = float(np.log2(1.25))  # the decision departs from the heuristic only for a 25 % predicted gain
+
+
+def choose(w, X, ncurr, k, fused=(0, 1), fused_limit=2048, heuristic_limit=2048, margin=MARGIN):
+    """The decision rule: the valid choice with the least predicted time, when it is
+    predicted faster than the heuristic's launch (fused up to heuristic_limit frontier
+    edges, else wide) by more than `margin` (log2 units); otherwise, and whenever an
+    output is not finite, the heuristic's launch.  Returns (choice, y) with y the
+    outputs, invalid choices set to +inf."""
     y, _ = forward(w, X, k)
     y = y.copy()
-    big = np.asarray(ncurr) > fused_limit
+    ncurr = np.asarray(ncurr)
+    h = np.where(ncurr <= heuristic_limit, 0, 2)
+    finite = np.all(np.isfinite(y), axis=1)
+    big = ncurr > fused_limit
     for c in fused:
         y[big, c] = np.inf
-    return np.argmin(y, axis=1), y
+    best = np.argmin(y, axis=1)
+    rows = np.arange(len(y))
+    use = finite & (y[rows, best] + margin < y[rows, h])
+    return np.where(use, best, h), y

@@ -10,6 +10,12 @@
 #pragma once
 #include "common.h"
 
+// The learned decision departs from the heuristic's launch only when the model
+// predicts the other launch at least 25 % faster: log2(1.25) in the model's units
+// (log2 microseconds).  Near the heuristic's threshold the two launches cost about
+// the same and the model's error would otherwise flip them back and forth.
+#define MLP_MARGIN 0.32192809f
+
 #define MLP_IN 6
 #define MLP_H 64
 #define MLP_OUT TRUSS_NUM_CHOICES

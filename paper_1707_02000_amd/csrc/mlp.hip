@@ -183,7 +183,8 @@ __global__ void k_mlp_init(const float* __restrict__ X, const float* __restrict_
   }
 }
 
-// Batched decisions with the peeling loop's own inference routine: one block per row.
+// Batched decisions with the peeling loop's own inference and decision routines:
+// one block per row.
 __global__ __launch_bounds__(MLP_H) void k_mlp_choose(const float* __restrict__ X, const i32* __restrict__ ncurr, int n,
                                                       const float* __restrict__ W, i32* __restrict__ choice,
                                                       float* __restrict__ Y) {
@@ -193,17 +194,9 @@ __global__ __launch_bounds__(MLP_H) void k_mlp_choose(const float* __restrict__ 
     __syncthreads();
     mlp_forward_block(W, sx, sy, ha, hb);
     if (threadIdx.x == 0) {
-      int best = -1;
-      float bv = INFINITY;
-      for (int k = 0; k < MLP_OUT; ++k) {
+      for (int k = 0; k < MLP_OUT; ++k)
         if (Y) Y[(size_t)r * MLP_OUT + k] = sy[k];
-        if ((k == TRUSS_CHOICE_FUSED || k == TRUSS_CHOICE_FUSED_NARROW) && ncurr[r] > SMALL_FRONTIER) continue;
-        if (isfinite(sy[k]) && sy[k] < bv) {
-          bv = sy[k];
-          best = k;
-        }
-      }
-      choice[r] = best;
+      choice[r] = mlp_decide(sy, ncurr[r]);
     }
     __syncthreads();
   }

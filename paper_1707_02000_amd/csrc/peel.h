@@ -1,5 +1,6 @@
 // Peeling (level loop) shared definitions.
 #pragma once
+#include "mlp.h"
 #include "truss.h"
 
 #define SCAN_ITEMS 16        // alive-list entries per thread per tile of a level scan
@@ -16,16 +17,35 @@
 #define ALONE_ALIVE 32768    // and scans alone when the alive list is at most this long
 #define GALLOP_K 8           // shorter-row entries per item when galloping
 #define DECIDE_THREADS 512   // threads of the one-block kernel that picks a round's launch
+#define LEARNED_MIN_FRONTIER 256  // the learned policy consults the model above this frontier size;
+                                  // smaller frontiers (most rounds) take the heuristic's launch: the
+                                  // features cost more there than a choice can gain
 #define CHOICE_NONE (-1)     // Ctl::choice while no launch is picked for the current frontier
 
-// Loop state published by k_decide for the pipelined host loop (host-mapped,
-// LOOP_SNAP_SLOTS slots by sequence number).
+// Loop state published by k_decide for the pipelined host loop, in host-mapped
+// slots (LOOP_SNAP_SLOTS, by sequence number).  Two 64-bit words per slot, each
+// carrying the low 24 bits of the sequence number, so the host checks each word
+// on its own and the device needs no fence between them:
+//   w0 = tag | ncurr << 24 | (choice + 1) << 55 | done << 59 | compact << 60
+//   w1 = tag | nalive << 24
+// (compact: under half of the working adjacency's edges are left).
 #define LOOP_SNAP_SLOTS 8
+#define SNAP_TAG_MASK 0xFFFFFFull
 struct LoopSnap {
-  i32 ncurr, choice, done, nalive, level, sublevels, processed, csr_edges;
-  i64 seq;
-  i64 pad[3];  // one 64-byte line per slot
+  u64 w0, w1;
+  u64 pad[6];  // one 64-byte line per slot
 };
+struct LoopState {
+  i32 ncurr, choice, done, nalive, compact;
+};
+
+__host__ __device__ __forceinline__ u64 snap_w0(i64 seq, i32 ncurr, i32 choice, i32 done, i32 compact) {
+  return ((u64)seq & SNAP_TAG_MASK) | ((u64)(u32)ncurr << 24) | ((u64)(u32)(choice + 1) << 55) |
+         ((u64)(done != 0) << 59) | ((u64)(compact != 0) << 60);
+}
+__host__ __device__ __forceinline__ u64 snap_w1(i64 seq, i32 nalive) {
+  return ((u64)seq & SNAP_TAG_MASK) | ((u64)(u32)nalive << 24);
+}
 
 // Everything a peeling kernel touches.
 struct PeelArgs {
@@ -38,15 +58,35 @@ struct PeelArgs {
   i32* S;
   u8* state;
   i32* order;  // truss_options::peel_round, or NULL
+  i64 m;  // edges
   int owner_higher;
   int single_round;
   const float* mlp;  // cost-model weights (TRUSS_VARIANT_LEARNED) or NULL
-  int want_features; // compute frontier features at each decision (learned policy or tracing)
+  int want_features; // frontier features: 0 never, 1 learned policy (large frontiers), 2 every decision (tracing)
 };
 
 __device__ __forceinline__ i32* cur_of(const PeelArgs& a, int sel) { return a.F[sel]; }
 __device__ __forceinline__ i32* next_of(const PeelArgs& a, int sel) { return a.F[sel == 2 ? 0 : sel + 1]; }
 __device__ __forceinline__ i32* prev_of(const PeelArgs& a, int sel) { return a.F[sel == 0 ? 2 : sel - 1]; }
+
+// The learned decision from the model's outputs y (log2 microseconds per
+// launch choice) for a frontier of ncurr edges: the valid choice predicted
+// fastest, if it beats the heuristic's launch by MLP_MARGIN; otherwise, and
+// whenever an output is not finite, the heuristic's launch.
+__device__ __forceinline__ int mlp_decide(const float* y, i32 ncurr) {
+  const int h = ncurr <= FUSED_THRESHOLD ? TRUSS_CHOICE_FUSED : TRUSS_CHOICE_WIDE;
+  int best = -1;
+  float bv = INFINITY;
+  for (int k = 0; k < TRUSS_NUM_CHOICES; ++k) {
+    if ((k == TRUSS_CHOICE_FUSED || k == TRUSS_CHOICE_FUSED_NARROW) && ncurr > SMALL_FRONTIER) continue;
+    if (!isfinite(y[k])) return h;
+    if (y[k] < bv) {
+      bv = y[k];
+      best = k;
+    }
+  }
+  return (best >= 0 && bv + MLP_MARGIN < y[h]) ? best : h;
+}
 
 namespace pkt {
 CsrSet csr_set(const Work& w);

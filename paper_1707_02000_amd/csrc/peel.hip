@@ -135,14 +135,28 @@ __device__ __forceinline__ int heuristic_choice(int policy, i32 ncurr) {
 }
 
 // Picks the launch of the round on the current frontier (ctl->ncurr > 0).
-// Features (learned policy or tracing only) come from up to FEAT_SAMPLE evenly
-// spaced frontier edges.  Called by every thread of one block (blockDim.x >=
+// Features (learned policy above LEARNED_MIN_FRONTIER edges, or tracing) come
+// from up to FEAT_SAMPLE evenly spaced frontier edges.  Called by every thread of one block (blockDim.x >=
 // MLP_H) after the control block's counts are final.
 __device__ void decide(const PeelArgs& a, float* sx, float* sy, float* ha, float* hb, int* schoice) {
   Ctl* ctl = a.ctl;
   __shared__ i64 s_sum_deg, s_sum_min, s_cnt;
   __shared__ i32 s_max, s_hist[32];
-  if (a.want_features) {
+  const bool feats = a.want_features == 2 || (a.want_features == 1 && ctl->ncurr > LEARNED_MIN_FRONTIER);
+  // With the model in use, its weights are loaded into registers first and
+  // staged in LDS after the features, so their load overlaps the feature reads.
+  constexpr int WPER = (MLP_NPARAM + DECIDE_THREADS - 1) / DECIDE_THREADS;
+  __shared__ float wl[MLP_NPARAM];
+  const bool use_mlp = ctl->policy == TRUSS_VARIANT_LEARNED && a.mlp && feats && blockDim.x == DECIDE_THREADS;
+  float wr[WPER];
+  if (use_mlp) {
+#pragma unroll
+    for (int k = 0; k < WPER; ++k) {
+      const int idx = threadIdx.x + k * DECIDE_THREADS;
+      wr[k] = idx < MLP_NPARAM ? a.mlp[idx] : 0.f;
+    }
+  }
+  if (feats) {
     if (threadIdx.x < 32) s_hist[threadIdx.x] = 0;
     if (threadIdx.x == 0) {
       s_sum_deg = s_sum_min = s_cnt = 0;
@@ -201,24 +215,25 @@ __device__ void decide(const PeelArgs& a, float* sx, float* sy, float* ha, float
   }
   __syncthreads();
   const int policy = ctl->policy;
-  if (policy == TRUSS_VARIANT_LEARNED && a.mlp && a.want_features) mlp_forward_block(a.mlp, sx, sy, ha, hb);
+  if (use_mlp) {
+#pragma unroll
+    for (int k = 0; k < WPER; ++k) {
+      const int idx = threadIdx.x + k * DECIDE_THREADS;
+      if (idx < MLP_NPARAM) wl[idx] = wr[k];
+    }
+    __syncthreads();
+    mlp_forward_block(wl, sx, sy, ha, hb);
+  } else if (policy == TRUSS_VARIANT_LEARNED && a.mlp && feats) {
+    mlp_forward_block(a.mlp, sx, sy, ha, hb);
+  }
   if (threadIdx.x == 0) {
     const i32 nc = ctl->ncurr;
     int c = heuristic_choice(policy, nc);
     if (policy == TRUSS_VARIANT_FIXED) {
       const int f = ctl->force_choice;
       if (f >= 0 && f < TRUSS_NUM_CHOICES && (!is_fused(f) || nc <= SMALL_FRONTIER)) c = f;
-    } else if (policy == TRUSS_VARIANT_LEARNED && a.mlp && a.want_features) {
-      int best = -1;
-      float bv = INFINITY;
-      for (int k = 0; k < MLP_OUT; ++k) {
-        if (is_fused(k) && nc > SMALL_FRONTIER) continue;
-        if (isfinite(sy[k]) && sy[k] < bv) {
-          bv = sy[k];
-          best = k;
-        }
-      }
-      if (best >= 0) c = best;  // otherwise the heuristic stands
+    } else if (policy == TRUSS_VARIANT_LEARNED && a.mlp && feats) {
+      c = mlp_decide(sy, nc);
     }
     ctl->choice = c;
     ctl->chosen[c] += 1;
@@ -495,23 +510,17 @@ __device__ __forceinline__ bool arrive_last(Ctl* ctl, int* slast, int nblk) {
 
 // ---------------------------------------------------------------- single block
 
-// Loop state for the host, written to host-mapped memory: the fields first,
-// then the sequence number with a system-scope release, which the host polls.
-__device__ __forceinline__ void publish_snap(const Ctl* ctl, LoopSnap* snap, i64 seq) {
-  LoopSnap* slot = snap + (seq & (LOOP_SNAP_SLOTS - 1));
-  slot->ncurr = ctl->ncurr;
-  slot->choice = ctl->choice;
-  slot->done = ctl->done;
-  slot->nalive = ctl->nalive;
-  slot->level = ctl->level;
-  slot->sublevels = ctl->sublevels;
-  slot->processed = ctl->processed;
-  slot->csr_edges = ctl->csr_edges;
-  __threadfence_system();
-  __hip_atomic_store(&slot->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-}
-
 namespace {
+
+// Loop state for the host: two self-tagged 64-bit words with system-scope
+// stores into the host-mapped slot of sequence seq.
+__device__ __forceinline__ void publish_snap(const PeelArgs& a, const Ctl* ctl, LoopSnap* snap, i64 seq) {
+  LoopSnap* slot = snap + (seq & (LOOP_SNAP_SLOTS - 1));
+  const i32 compact = (a.m - ctl->processed) * 2 < (i64)ctl->csr_edges;
+  __hip_atomic_store(&slot->w0, snap_w0(seq, ctl->ncurr, ctl->choice, ctl->done, compact), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_SYSTEM);
+  __hip_atomic_store(&slot->w1, snap_w1(seq, ctl->nalive), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
 
 // LDS of a block that may go on alone (P: work prefix of a small frontier).
 template <int NT>
@@ -931,7 +940,7 @@ __global__ __launch_bounds__(DECIDE_THREADS) void k_decide(PeelArgs a, i64 seq, 
   if (go) leave<DECIDE_THREADS>(a, s);
   if (publish) {
     __syncthreads();
-    if (threadIdx.x == 0) publish_snap(ctl, ctl->snap, seq);
+    if (threadIdx.x == 0) publish_snap(a, ctl, ctl->snap, seq);
   }
 }
 
@@ -1024,10 +1033,11 @@ PeelArgs peel_args(const Work& w, const truss_options& opt) {
   a.S = w.S;
   a.state = w.state;
   a.order = opt.peel_round;
+  a.m = w.m;
   a.owner_higher = opt.owner_rule == 1;
   a.single_round = opt.single_round != 0;
   a.mlp = opt.mlp_weights;
-  a.want_features = (opt.variant == TRUSS_VARIANT_LEARNED) || opt.trace != nullptr;
+  a.want_features = opt.trace != nullptr ? 2 : (opt.variant == TRUSS_VARIANT_LEARNED ? 1 : 0);
   return a;
 }
 
@@ -1146,28 +1156,26 @@ truss_status snap_buffers() {
   if (h_snap) return TRUSS_OK;
   PKT_HIP(hipHostMalloc((void**)&h_snap, sizeof(LoopSnap) * LOOP_SNAP_SLOTS,
                         hipHostMallocMapped | hipHostMallocCoherent));
-  memset(h_snap, 0, sizeof(LoopSnap) * LOOP_SNAP_SLOTS);
-  for (int i = 0; i < LOOP_SNAP_SLOTS; ++i) h_snap[i].seq = -1;
+  memset(h_snap, 0xff, sizeof(LoopSnap) * LOOP_SNAP_SLOTS);
   PKT_HIP(hipHostGetDevicePointer((void**)&d_snap, h_snap, 0));
   return TRUSS_OK;
 }
 
 // Waits for the state published by sequence k.  Polls the slot; checks now and
 // then whether the stream has drained without it (an error, not a hang).
-truss_status wait_snap(i64 k, hipStream_t s, LoopSnap* out) {
-  volatile LoopSnap* slot = h_snap + (k & (LOOP_SNAP_SLOTS - 1));
+truss_status wait_snap(i64 k, hipStream_t s, LoopState* out) {
+  LoopSnap* slot = h_snap + (k & (LOOP_SNAP_SLOTS - 1));
+  const u64 tag = (u64)k & SNAP_TAG_MASK;
   auto t_check = std::chrono::steady_clock::now();
   for (;;) {
-    if (__atomic_load_n(&h_snap[k & (LOOP_SNAP_SLOTS - 1)].seq, __ATOMIC_ACQUIRE) == k) {
-      out->ncurr = slot->ncurr;
-      out->choice = slot->choice;
-      out->done = slot->done;
-      out->nalive = slot->nalive;
-      out->level = slot->level;
-      out->sublevels = slot->sublevels;
-      out->processed = slot->processed;
-      out->csr_edges = slot->csr_edges;
-      out->seq = k;
+    const u64 w0 = __atomic_load_n(&slot->w0, __ATOMIC_ACQUIRE);
+    const u64 w1 = __atomic_load_n(&slot->w1, __ATOMIC_ACQUIRE);
+    if ((w0 & SNAP_TAG_MASK) == tag && (w1 & SNAP_TAG_MASK) == tag) {
+      out->ncurr = (i32)((w0 >> 24) & 0x7FFFFFFFull);
+      out->choice = (i32)((w0 >> 55) & 0xFull) - 1;
+      out->done = (i32)((w0 >> 59) & 1ull);
+      out->compact = (i32)((w0 >> 60) & 1ull);
+      out->nalive = (i32)((w1 >> 24) & 0x7FFFFFFFull);
       return TRUSS_OK;
     }
     const auto now = std::chrono::steady_clock::now();
@@ -1175,7 +1183,8 @@ truss_status wait_snap(i64 k, hipStream_t s, LoopSnap* out) {
       t_check = now;
       const hipError_t q = hipStreamQuery(s);
       if (q == hipSuccess) {
-        if (__atomic_load_n(&h_snap[k & (LOOP_SNAP_SLOTS - 1)].seq, __ATOMIC_ACQUIRE) == k) continue;
+        const u64 v0 = __atomic_load_n(&slot->w0, __ATOMIC_ACQUIRE), v1 = __atomic_load_n(&slot->w1, __ATOMIC_ACQUIRE);
+        if ((v0 & SNAP_TAG_MASK) == tag && (v1 & SNAP_TAG_MASK) == tag) continue;
         set_error("loop state %lld was not published", (long long)k);
         return TRUSS_E_INTERNAL;
       }
@@ -1184,17 +1193,13 @@ truss_status wait_snap(i64 k, hipStream_t s, LoopSnap* out) {
   }
 }
 
-inline LoopSnap snap_of(const Ctl& c) {
-  LoopSnap x;
-  memset(&x, 0, sizeof(x));
+inline LoopState state_of(const Ctl& c, i64 m) {
+  LoopState x;
   x.ncurr = c.ncurr;
   x.choice = c.choice;
   x.done = c.done;
   x.nalive = c.nalive;
-  x.level = c.level;
-  x.sublevels = c.sublevels;
-  x.processed = c.processed;
-  x.csr_edges = c.csr_edges;
+  x.compact = (m - c.processed) * 2 < (i64)c.csr_edges;
   return x;
 }
 
@@ -1313,7 +1318,7 @@ truss_status run_single(const Work& w, const truss_options& opt, truss_stats* st
     };
     Flight fl[PIPE_MAX];
     int nfl = 0;
-    LoopSnap cur = snap_of(hc);
+    LoopState cur = state_of(hc, w.m);
     int after_scan = SEQ_WIDE;  // kind of the round that followed the last level scan
     auto guess_after = [&](int kind) { return kind == SEQ_SCAN ? after_scan : (kind == SEQ_DECIDE ? SEQ_WIDE : kind); };
     // Tops the pipeline up to `depth` sequences.  The sequences in flight are
@@ -1346,7 +1351,7 @@ truss_status run_single(const Work& w, const truss_options& opt, truss_stats* st
       const Flight f = fl[0];
       for (int i = 1; i < nfl; ++i) fl[i - 1] = fl[i];
       --nfl;
-      const LoopSnap prev = cur;
+      const LoopState prev = cur;
       st = wait_snap(f.seq, s, &cur);
       if (st) return st;
       if (cur.done) break;
@@ -1358,14 +1363,14 @@ truss_status run_single(const Work& w, const truss_options& opt, truss_stats* st
         const int k = seq_kind(cur.ncurr, cur.choice);
         if (k == SEQ_FUSED || k == SEQ_WIDE) after_scan = k;
       }
-      if (opt.compact && (i64)(w.m - cur.processed) * 2 < (i64)cur.csr_edges) {
+      if (opt.compact && cur.compact) {
         PKT_HIP(hipStreamSynchronize(s));  // lets the sequences in flight finish
         nfl = 0;
         st = read_ctl(w, &hc, s);
         if (st) return st;
         st = maybe_compact();
         if (st) return st;
-        cur = snap_of(hc);
+        cur = state_of(hc, w.m);
         if (cur.done) break;
       }
       st = fill();

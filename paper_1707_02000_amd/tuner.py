@@ -164,6 +164,18 @@ def choose_batch(W, X, ncurr):
     return C.cpu().numpy(), Y.cpu().numpy()
 
 
+LEARNED_MIN_FRONTIER = 256  # the library consults the model above this frontier size
+
+
+def learned_choices(W, rounds):
+    """The learned policy's choice for every traced round, as the peeling loop makes it:
+    the model above LEARNED_MIN_FRONTIER frontier edges, the heuristic below."""
+    X, _, _, nc = dataset(rounds)
+    c, _ = choose_batch(W, X, nc)
+    return [int(ci) if r["frontier"] > LEARNED_MIN_FRONTIER else heuristic_choice(r["frontier"])
+            for ci, r in zip(c, rounds)]
+
+
 def save_weights(W, path=DEFAULT_WEIGHTS, meta=None):
     os.makedirs(os.path.dirname(path), exist_ok=True)
     w = W.cpu().numpy() if hasattr(W, "cpu") else np.asarray(W)
@@ -213,8 +225,7 @@ def main(argv=None):
     thr, scores = autotune_threshold(train_rounds)
     X, T, M, nc = dataset(train_rounds)
     W, hist = train(X, T, M, steps=args.steps, lr=args.lr)
-    choice, _ = choose_batch(W, X, nc)
-    it = iter(choice)
+    it = iter(learned_choices(W, train_rounds))
     report["autotuned_threshold"] = thr
     report["threshold_scores_us"] = {str(k): v for k, v in scores.items()}
     report["train"] = {"rounds": len(train_rounds), "loss_first": float(hist[0]), "loss_last": float(hist[-1]),
@@ -224,9 +235,7 @@ def main(argv=None):
     for name in args.held_out:
         g = _graph_for(name)
         r = collect_rounds(g.offsets, g.adj, repeats=args.repeats)
-        Xh, _, _, nch = dataset(r)
-        ch, _ = choose_batch(W, Xh, nch)
-        it = iter(ch)
+        it = iter(learned_choices(W, r))
         report["held_out"][name] = {"rounds": len(r), "learned": evaluate(r, lambda q: int(next(it))),
                                     "heuristic": evaluate(r, lambda q: heuristic_choice(q["frontier"], thr))}
         print("held out", name, report["held_out"][name], flush=True)

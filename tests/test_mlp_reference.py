@@ -55,4 +55,16 @@ def test_choose_respects_validity():
     ncurr = np.where(np.arange(50) % 2 == 0, 100, 100000)
     c, y = mlp.choose(w, X, ncurr, K)
     assert np.all(np.isin(c[ncurr > 2048], [2, 3, 4]))
-    assert np.all(c == np.argmin(y, axis=1))
+    rows = np.arange(50)
+    h = np.where(ncurr <= 2048, 0, 2)
+    best = np.argmin(y, axis=1)
+    departs = y[rows, best] + mlp.MARGIN < y[rows, h]
+    assert np.all(c[departs] == best[departs]) and np.all(c[~departs] == h[~departs])
+    # with no margin the rule is the plain argmin over valid choices
+    c0, y0 = mlp.choose(w, X, ncurr, K, margin=0.0)
+    assert np.all(c0 == np.argmin(y0, axis=1))
+    # a non-finite output keeps the heuristic's launch
+    w_bad = w.copy()
+    w_bad[-1] = np.nan
+    cb, _ = mlp.choose(w_bad, X, ncurr, K)
+    assert np.all(cb == h)
