@@ -60,7 +60,7 @@ typedef enum {
 /* How each frontier round (sub-level) of the peeling is launched.  Every choice
  * gives the same trussness; only the running time differs. */
 typedef enum {
-  TRUSS_CHOICE_FUSED = 0,        /* one launch, 256 blocks: work prefix in LDS, items, finalize
+  TRUSS_CHOICE_FUSED = 0,        /* one launch, 512 blocks: work prefix in LDS, items, finalize
                                     (frontiers of at most 2048 edges) */
   TRUSS_CHOICE_FUSED_NARROW = 1, /* the same with 32 blocks */
   TRUSS_CHOICE_WIDE = 2,         /* device scan of per-edge work, then 2048 blocks of items

@@ -5,16 +5,30 @@
 
 #define SCAN_ITEMS 16        // alive-list entries per thread per tile of a level scan
 #define SMALL_FRONTIER 2048  // frontiers up to this size may run as one fused launch
-#define FUSED_THRESHOLD 2048 // the heuristic fuses up to this size (end-to-end runs of the tuner's
-                             // candidates: the fused launch's continuation favours the largest)
 #define SMALL_THREADS 512    // threads per block of the fused launch
-#define FUSED_BLOCKS 256     // blocks of TRUSS_CHOICE_FUSED
 #define FUSED_NARROW_BLOCKS 32
-#define WIDE_BLOCKS 2048     // blocks of TRUSS_CHOICE_WIDE
 #define WIDE_NARROW_BLOCKS 256
-#define ALONE_FRONTIER 512   // the fused launch's last block goes on alone on frontiers up to this size,
-#define ALONE_ITEMS 2048     // with at most this many intersection items,
-#define ALONE_ALIVE 32768    // and scans alone when the alive list is at most this long
+// Launch constants a build may override (tuning runs):
+#ifndef FUSED_THRESHOLD
+#define FUSED_THRESHOLD 2048  // the heuristic fuses up to this size (end-to-end runs of the tuner's
+                              // candidates: the single-block continuation favours the largest)
+#endif
+#ifndef FUSED_BLOCKS
+#define FUSED_BLOCKS 512      // blocks of TRUSS_CHOICE_FUSED (measured: 512 beats 256 and 1024)
+#endif
+#ifndef WIDE_BLOCKS
+#define WIDE_BLOCKS 2048      // blocks of TRUSS_CHOICE_WIDE
+#endif
+// Single-block continuation (host-driven loop only; see peel_args):
+#ifndef ALONE_FRONTIER
+#define ALONE_FRONTIER 512    // the deciding block goes on alone on frontiers up to this size,
+#endif
+#ifndef ALONE_ITEMS
+#define ALONE_ITEMS 2048      // with at most this many intersection items,
+#endif
+#ifndef ALONE_ALIVE
+#define ALONE_ALIVE 32768     // and scans alone when the alive list is at most this long
+#endif
 #define GALLOP_K 8           // shorter-row entries per item when galloping
 #define DECIDE_THREADS 512   // threads of the one-block kernel that picks a round's launch
 #define LEARNED_MIN_FRONTIER 256  // the learned policy consults the model above this frontier size;
@@ -59,6 +73,7 @@ struct PeelArgs {
   u8* state;
   i32* order;  // truss_options::peel_round, or NULL
   i64 m;  // edges
+  i32 alone_frontier, alone_items, alone_alive;  // single-block continuation limits (0: none)
   int owner_higher;
   int single_round;
   const float* mlp;  // cost-model weights (TRUSS_VARIANT_LEARNED) or NULL

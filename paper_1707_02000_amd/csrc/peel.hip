@@ -534,8 +534,9 @@ struct AloneLds {
 };
 
 // The last block of a round or level scan goes on alone while the work stays
-// small: rounds of at most ALONE_FRONTIER edges and ALONE_ITEMS items, and level
-// scans of at most ALONE_ALIVE entries.  It stops at once with single_round.
+// small: rounds of at most PeelArgs::alone_frontier edges and alone_items items,
+// and level scans of at most alone_alive entries.  It stops at once with
+// single_round.
 // On return the control block says what is left (ncurr > 0: a frontier whose
 // launch is still to be picked; ncurr == 0: a level scan; or done).
 template <int NT>
@@ -548,7 +549,7 @@ __device__ void go_alone(const PeelArgs& a, AloneLds<NT>& s) {
     const i32 l = s.v.level, sel = s.v.sel, r = s.v.r;
     i32* curr = cur_of(a, sel);
     if (s.v.ncurr == 0) {
-      if (s.v.nalive > ALONE_ALIVE) break;
+      if (s.v.nalive > a.alone_alive) break;
       const i32* A = s.v.asel ? a.A1 : a.A0;
       i32* Aout = s.v.asel ? a.A0 : a.A1;
       i32 mn = INT_MAX;
@@ -562,11 +563,11 @@ __device__ void go_alone(const PeelArgs& a, AloneLds<NT>& s) {
       __syncthreads();
       continue;
     }
-    if (s.v.ncurr > ALONE_FRONTIER) break;
+    if (s.v.ncurr > a.alone_frontier) break;
     const Csr c = a.csr.pick(s.v.csel);
     i32* next = next_of(a, sel);
     const i64 total = lds_work_prefix<NT>(a, c, curr, s.v.ncurr, l, s.v.variant, s.P, s.tmp);
-    if (total > ALONE_ITEMS) break;
+    if (total > a.alone_items) break;
     mark_prev(a, sel, s.v.nprev, threadIdx.x, NT);
     lds_items<NT>(a, c, curr, s.v.ncurr, l, r, s.v.variant, s.P, total, 0, NT, next);
     __syncthreads();  // every wave's appends are counted before the count is read
@@ -1034,6 +1035,13 @@ PeelArgs peel_args(const Work& w, const truss_options& opt) {
   a.state = w.state;
   a.order = opt.peel_round;
   a.m = w.m;
+  // The single-block continuation saves host round trips; with launch sequences
+  // guessed ahead (pipelined loop) there are none to save and the full grid is
+  // faster, so it is off there.
+  const bool cont = opt.device_loop != 3 || opt.trace != nullptr;
+  a.alone_frontier = cont ? ALONE_FRONTIER : 0;
+  a.alone_items = cont ? ALONE_ITEMS : 0;
+  a.alone_alive = cont ? ALONE_ALIVE : 0;
   a.owner_higher = opt.owner_rule == 1;
   a.single_round = opt.single_round != 0;
   a.mlp = opt.mlp_weights;
