@@ -252,9 +252,9 @@ __device__ void decide(const PeelArgs& a, float* sx, float* sy, float* ha, float
 // rule on both other edges (rd: the round index).  Edges that reached l come
 // back in x0, x1 for a wave-aggregated append; more than two from one item are
 // appended at once.
-__device__ __forceinline__ void psl_item(const PeelArgs& a, const Csr& c, i32 e1, i64 t, i32 l, i32 rd, int variant,
-                                         i32& x0, i32& x1, i32* spill_next, i32* spill_ctr) {
-  const Rows r = rows_of(c, a.el[e1]);
+__device__ __forceinline__ void psl_item_rows(const PeelArgs& a, const Csr& c, i32 e1, const Rows& r, i64 t, i32 l,
+                                              i32 rd, int variant, i32& x0, i32& x1, i32* spill_next,
+                                              i32* spill_ctr) {
   const i64 k = chunk_of(variant);
   const i64 j0 = r.sb + t * k, j1 = min(r.sb + r.slen, j0 + k);
   i64 p = r.lb;
@@ -283,6 +283,11 @@ __device__ __forceinline__ void psl_item(const PeelArgs& a, const Csr& c, i32 e1
         spill_next[atomicAdd(spill_ctr, 1)] = y[q];
     }
   }
+}
+
+__device__ __forceinline__ void psl_item(const PeelArgs& a, const Csr& c, i32 e1, i64 t, i32 l, i32 rd, int variant,
+                                         i32& x0, i32& x1, i32* spill_next, i32* spill_ctr) {
+  psl_item_rows(a, c, e1, rows_of(c, a.el[e1]), t, l, rd, variant, x0, x1, spill_next, spill_ctr);
 }
 
 __device__ __forceinline__ void append_next(i32 x0, i32 x1, i32* next, i32* counter) {
@@ -426,11 +431,19 @@ __device__ __forceinline__ void mark_prev(const PeelArgs& a, int sel, i32 nprev,
   for (i64 i = tid; i < nprev; i += stride) a.state[prev[i]] = ST_PROC;
 }
 
+// Rows of the frontier edges of a fused round, kept in LDS so that an item
+// reads its edge from there instead of three dependent global loads.
+struct EdgeRows {
+  i64 sb[SMALL_FRONTIER], lb[SMALL_FRONTIER];
+  i32 e1[SMALL_FRONTIER], L[SMALL_FRONTIER], slen[SMALL_FRONTIER];
+};
+
 // Exclusive prefix of the work of frontier edges [0, nc) into LDS P[0..nc]
-// (nc <= SMALL_FRONTIER); returns the total.  Every thread of the block calls it.
+// (nc <= SMALL_FRONTIER); returns the total.  With er, also each edge's rows.
+// Every thread of the block calls it.
 template <int NT>
 __device__ i64 lds_work_prefix(const PeelArgs& a, const Csr& c, const i32* curr, i32 nc, i32 l, int variant, i64* P,
-                               i64* tmp) {
+                               i64* tmp, EdgeRows* er = nullptr) {
   constexpr int PER = SMALL_FRONTIER / NT;
   const int i0 = threadIdx.x * PER;
   i64 w[PER];
@@ -438,7 +451,20 @@ __device__ i64 lds_work_prefix(const PeelArgs& a, const Csr& c, const i32* curr,
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
     const int i = i0 + k;
-    w[k] = (i < nc) ? work_of(a, c, curr[i], l, variant) : 0;
+    w[k] = 0;
+    if (i < nc && l > 0) {  // level 0: no items (work_of)
+      const i32 e1 = curr[i];
+      const Rows r = rows_of(c, a.el[e1]);
+      const i64 ck = chunk_of(variant);
+      w[k] = (r.slen + ck - 1) / ck;
+      if (er) {
+        er->e1[i] = e1;
+        er->sb[i] = r.sb;
+        er->lb[i] = r.lb;
+        er->L[i] = (i32)(r.le - r.lb);
+        er->slen[i] = (i32)r.slen;
+      }
+    }
     sum += w[k];
   }
   i64 tot;
@@ -454,16 +480,26 @@ __device__ i64 lds_work_prefix(const PeelArgs& a, const Csr& c, const i32* curr,
   return tot;
 }
 
-// Items [base, total) with the given stride, pairs located through LDS P.
+// Items [base, total) with the given stride, pairs located through LDS P (and
+// the edges' rows from LDS when er is given).
 template <int NT>
 __device__ void lds_items(const PeelArgs& a, const Csr& c, const i32* curr, i32 nc, i32 l, i32 r, int variant,
-                          const i64* P, i64 total, i64 base, i64 stride, i32* next) {
+                          const i64* P, i64 total, i64 base, i64 stride, i32* next, const EdgeRows* er = nullptr) {
   for (i64 b = base; b < total; b += stride) {
     const i64 g = b + threadIdx.x;
     i32 x0 = -1, x1 = -1;
     if (g < total) {
       const i64 i = upper_bound_dev(P, (i64)0, (i64)nc + 1, g) - 1;
-      psl_item(a, c, curr[i], g - P[i], l, r, variant, x0, x1, next, &a.ctl->nnext);
+      if (er) {
+        Rows rw;
+        rw.sb = er->sb[i];
+        rw.slen = er->slen[i];
+        rw.lb = er->lb[i];
+        rw.le = rw.lb + er->L[i];
+        psl_item_rows(a, c, er->e1[i], rw, g - P[i], l, r, variant, x0, x1, next, &a.ctl->nnext);
+      } else {
+        psl_item(a, c, curr[i], g - P[i], l, r, variant, x0, x1, next, &a.ctl->nnext);
+      }
     }
     append_next(x0, x1, next, &a.ctl->nnext);
   }
@@ -580,10 +616,12 @@ __device__ void go_alone(const PeelArgs& a, AloneLds<NT>& s) {
 // launch of the frontier left, if any.
 template <int NT>
 __device__ void leave(const PeelArgs& a, AloneLds<NT>& s) {
-  go_alone<NT>(a, s);
+  if (a.alone_frontier > 0 || a.alone_alive > 0) {  // else s.v is current already
+    go_alone<NT>(a, s);
+    load_view(a.ctl, &s.v);
+  }
   __shared__ float sx[8], sy[MLP_OUT], ha[MLP_H], hb[MLP_H];
   __shared__ int schoice;
-  load_view(a.ctl, &s.v);
   if (!s.v.done && s.v.ncurr > 0) decide(a, sx, sy, ha, hb, &schoice);
 }
 
@@ -752,6 +790,7 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_psl_small(PeelArgs a) {
   Ctl* ctl = a.ctl;
   __shared__ i64 P[SMALL_FRONTIER + 1];
   __shared__ i64 tmp[SMALL_THREADS / PKT_WAVE];
+  __shared__ EdgeRows er;
   __shared__ CtlView v;
   load_view(ctl, &v);
   if (v.done || v.ncurr == 0 || v.ncurr > SMALL_FRONTIER || !is_fused(v.choice)) return;
@@ -763,9 +802,9 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_psl_small(PeelArgs a) {
   i32* next = next_of(a, sel);
   if (blockIdx.x == 0 && threadIdx.x == 0) ctl->round_done = 1;
   mark_prev(a, sel, v.nprev, (i64)blockIdx.x * SMALL_THREADS + threadIdx.x, (i64)nblk * SMALL_THREADS);
-  const i64 total = lds_work_prefix<SMALL_THREADS>(a, c, curr, nc, l, v.variant, P, tmp);
+  const i64 total = lds_work_prefix<SMALL_THREADS>(a, c, curr, nc, l, v.variant, P, tmp, &er);
   lds_items<SMALL_THREADS>(a, c, curr, nc, l, r, v.variant, P, total, (i64)blockIdx.x * SMALL_THREADS,
-                           (i64)nblk * SMALL_THREADS, next);
+                           (i64)nblk * SMALL_THREADS, next, &er);
 }
 
 // Work of frontier edge i for the device-wide scan (wide rounds above level 0).
@@ -932,9 +971,12 @@ __global__ __launch_bounds__(DECIDE_THREADS) void k_decide(PeelArgs a, i64 seq, 
   bool go = !s.v.done && (s.v.round_done || s.v.choice == CHOICE_NONE);
   if (go && s.v.round_done) {
     if (threadIdx.x == 0) {
-      ctl_after_sublevel(ctl, s.v.ncurr, ctl->nnext, s.v.sel);
+      const i32 nn = ctl->nnext;
+      ctl_after_sublevel(ctl, s.v.ncurr, nn, s.v.sel);
       ctl->round_done = 0;
       ctl->choice = CHOICE_NONE;
+      s.v.ncurr = nn;  // the view's fields leave() reads
+      s.v.choice = CHOICE_NONE;
     }
     __syncthreads();
   }
