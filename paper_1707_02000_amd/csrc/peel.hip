@@ -43,29 +43,50 @@ namespace {
 // seen from frontier edge e1 in round r: x loses one unit if its support is
 // above l and e1 owns the triangle (y is not in the frontier, or e1 has the
 // lower id -- the higher id with owner_higher).  The atomic's old value decides:
-// l + 1 means x now sits at l and joins the next frontier (tag of round r + 1); <= l
-// means the decrement overshot (another thread got there first) and is undone.
-// Returns x if it joined the next frontier, else -1.  The plain pre-read of S
-// may be stale: while S[x] > l every older value is > l too, and once S[x] <= l
-// it stays <= l for the level, so a stale read can only cause a decrement that
-// is then undone.  y_curr comes from the caller's earlier read of y's state:
-// during a round a state can only change between values that are not the
-// round's tag (alive -> next, previous round -> processed), so that read
-// answers "is y current" for the whole round.  The next-frontier tag written
-// here reads as "not current" and "not processed" to every other thread.
-__device__ __forceinline__ i32 psl_rule(i32 x, bool y_curr, i32 y, i32 e1, i32 l, i32 r, i32* S, u8* state,
-                                        i32* order, int owner_higher) {
-  if (atomic_load_relaxed(&S[x]) <= l) return -1;
-  const bool mine = !y_curr || (owner_higher ? (e1 > y) : (e1 < y));
-  if (!mine) return -1;
-  const i32 a = atomicSub(&S[x], 1);
-  if (a == l + 1) {
-    state[x] = round_tag(r + 1);
-    if (order) order[x] = r + 1;
-    return x;
+// l + 1 means x now sits at l and joins the next frontier (tag of round r + 1);
+// <= l means the decrement overshot (another thread got there first) and is
+// undone.  The plain pre-read of S may be stale: while S[x] > l every older value
+// is > l too, and once S[x] <= l it stays <= l for the level, so a stale read can
+// only cause a decrement that is then undone.  Whether y is current comes from
+// the caller's earlier read of y's state: during a round a state only changes
+// between values that are not the round's tag (alive -> next, previous round ->
+// processed), so that read answers for the whole round.  The next-frontier tag
+// written here reads as "not current" and "not processed" to every other thread.
+//
+// Applied to both other edges es, eo of one triangle (states ss, so): (x, y) =
+// (es, eo) and (eo, es), with the two edges' memory operations interleaved --
+// both pre-reads, then both atomics -- so their round trips overlap (different
+// words: their order does not matter).  xa / xb get es / eo if they joined the
+// next frontier, else -1.
+__device__ __forceinline__ void psl_tri(i32 es, u8 ss, i32 eo, u8 so, i32 e1, i32 l, i32 r, i32* S, u8* state,
+                                        i32* order, int owner_higher, i32& xa, i32& xb) {
+  const u8 tcur = round_tag(r);
+  const bool own_s = so != tcur || (owner_higher ? (e1 > eo) : (e1 < eo));
+  const bool own_o = ss != tcur || (owner_higher ? (e1 > es) : (e1 < es));
+  const i32 vs = own_s ? atomic_load_relaxed(&S[es]) : l;
+  const i32 vo = own_o ? atomic_load_relaxed(&S[eo]) : l;
+  const bool ds = vs > l, dd = vo > l;
+  const i32 as = ds ? atomicSub(&S[es], 1) : 0;
+  const i32 ao = dd ? atomicSub(&S[eo], 1) : 0;
+  xa = xb = -1;
+  if (ds) {
+    if (as == l + 1) {
+      state[es] = round_tag(r + 1);
+      if (order) order[es] = r + 1;
+      xa = es;
+    } else if (as <= l) {
+      atomicAdd(&S[es], 1);
+    }
   }
-  if (a <= l) atomicAdd(&S[x], 1);
-  return -1;
+  if (dd) {
+    if (ao == l + 1) {
+      state[eo] = round_tag(r + 1);
+      if (order) order[eo] = r + 1;
+      xb = eo;
+    } else if (ao <= l) {
+      atomicAdd(&S[eo], 1);
+    }
+  }
 }
 
 // Shorter and longer working rows of frontier edge e1 = (u, v).
@@ -258,7 +279,6 @@ __device__ __forceinline__ void psl_item_rows(const PeelArgs& a, const Csr& c, i
   const i64 k = chunk_of(variant);
   const i64 j0 = r.sb + t * k, j1 = min(r.sb + r.slen, j0 + k);
   i64 p = r.lb;
-  const u8 tcur = round_tag(rd);
   for (i64 j = j0; j < j1; ++j) {
     const i32 es = c.eid[j];
     const u8 ss = a.state[es];
@@ -271,8 +291,8 @@ __device__ __forceinline__ void psl_item_rows(const PeelArgs& a, const Csr& c, i
     ++p;
     const u8 so = a.state[eo];
     if (is_processed(so, rd)) continue;
-    const i32 y[2] = {psl_rule(es, so == tcur, eo, e1, l, rd, a.S, a.state, a.order, a.owner_higher),
-                      psl_rule(eo, ss == tcur, es, e1, l, rd, a.S, a.state, a.order, a.owner_higher)};
+    i32 y[2];
+    psl_tri(es, ss, eo, so, e1, l, rd, a.S, a.state, a.order, a.owner_higher, y[0], y[1]);
     for (int q = 0; q < 2; ++q) {
       if (y[q] < 0) continue;
       if (x0 < 0)
@@ -886,9 +906,7 @@ __device__ void tile_one_edge(const PeelArgs& a, const Csr& c, const i32* curr, 
       const i32 es = c.eid[j], eo = c.eid[p];
       const u8 ss = a.state[es], so = a.state[eo];
       if (!is_processed(ss, r) && !is_processed(so, r)) {
-        const u8 tcur = round_tag(r);
-        x0 = psl_rule(es, so == tcur, eo, te.e1, l, r, a.S, a.state, a.order, a.owner_higher);
-        x1 = psl_rule(eo, ss == tcur, es, te.e1, l, r, a.S, a.state, a.order, a.owner_higher);
+        psl_tri(es, ss, eo, so, te.e1, l, r, a.S, a.state, a.order, a.owner_higher, x0, x1);
       }
     }
   }
