@@ -348,7 +348,8 @@ def edge_list(offsets, adj, *, stream=None):
 
 
 def truss_decompose_batched(vtx_off, adj_off, offsets_packed, adj_packed, *, variant="auto", validate=True,
-                            sequential=False, stream=None, workspace=None, out=None, return_stats=False):
+                            sequential=False, stream=None, workspace=None, out=None, return_stats=False,
+                            device_loop="pipelined", mlp_weights=None):
     """Trussness of many packed graphs (layout of include/pkt.h); int32 [sum m_g] CUDA tensor."""
     torch = _torch()
     lib = load()
@@ -358,7 +359,7 @@ def truss_decompose_batched(vtx_off, adj_off, offsets_packed, adj_packed, *, var
     ap = _dev(adj_packed, torch.int32, torch)
     G = vo.numel() - 1
     total_vtx, total_adj = int(op.numel()), int(ap.numel())
-    opt = make_options(variant, True, validate)
+    opt = make_options(variant, device_loop, validate, mlp_weights=mlp_weights)
     opt.batch_sequential = int(bool(sequential))
     if workspace is None:
         nb = ctypes.c_size_t(0)

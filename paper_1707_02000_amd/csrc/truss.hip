@@ -144,7 +144,12 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_orient(i32 n, i64 two_m, const i6
 // ------------------------------------------------------------------ support
 
 #define SUP_THREADS 256
-#define SUP_DMAX 2048          // largest out-row staged in LDS
+#ifndef SUP_DMAX
+#define SUP_DMAX 1024          // largest out-row hashed in LDS (16 KB of LDS per block: 8 blocks
+#endif                         // per CU; 2048 measured 1.6x slower for the lost occupancy)
+#ifndef SUP_BLOCKS
+#define SUP_BLOCKS 2048        // workgroups of the support kernel (they drain a work queue)
+#endif
 #define SUP_TBL (2 * SUP_DMAX)  // hash slots (power of two)
 #define SUP_CHUNK 8             // vertices taken from the work queue at a time
 
@@ -156,25 +161,46 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_orient(i32 n, i64 two_m, const i6
 // N+(v) for every v in N+(u), and probes each w there.  Each triangle adds one
 // to its three edges: edge (v, w) by a global atomic, edges (u, v) and (u, w)
 // through LDS counters per slot of N+(u), flushed once per u.  Rows longer than
-// SUP_DMAX take a slower path with global binary searches.  Vertices come from
+// SUP_DMAX take a path with binary searches instead.  Vertices come from
 // an atomic work queue in chunks (dynamic scheduling).
-// Long out-row: every pair (v, w), v in N+(u), w in N+(v), checked by a binary
-// search of w in N+(u); all three edges by global atomics.
-__device__ void support_long_row(i32 u, i64 b, i32 d, const i64* __restrict__ ooff, const i32* __restrict__ oadj,
-                                 const i32* __restrict__ oeid, i32* __restrict__ S) {
-  for (i32 i = 0; i < d; ++i) {
+// Long out-row (more than SUP_DMAX entries): one wave per v in N+(u), lanes over
+// N+(v), each w looked up by binary search in N+(u) -- staged sorted in LDS (the
+// hash table's space) when it fits in 2 * SUP_DMAX entries, else in memory; all
+// three edges by global atomics.
+__device__ void support_long_row(i32 b_u, i64 b, i32 d, const i64* __restrict__ ooff, const i32* __restrict__ oadj,
+                                 const i32* __restrict__ oeid, i32* __restrict__ S, i32* lds) {
+  const bool staged = d <= 2 * SUP_DMAX;
+  if (staged) {
+    for (int i = threadIdx.x; i < d; i += SUP_THREADS) lds[i] = oadj[b + i];
+    __syncthreads();
+  }
+  const int lane = lane_id(), wid = threadIdx.x / PKT_WAVE;
+  for (i32 i = wid; i < d; i += SUP_THREADS / PKT_WAVE) {
     const i32 v = oadj[b + i];
     const i64 vb = ooff[v], ve = ooff[v + 1];
-    for (i64 k = vb + threadIdx.x; k < ve; k += blockDim.x) {
+    i32 c_uv = 0;
+    for (i64 k = vb + lane; k < ve; k += PKT_WAVE) {
       const i32 w = oadj[k];
-      const i64 p = lower_bound_dev(oadj, b, b + d, w);
-      if (p < b + d && oadj[p] == w) {
-        atomicAdd(&S[oeid[b + i]], 1);
-        atomicAdd(&S[oeid[p]], 1);
-        atomicAdd(&S[oeid[k]], 1);
+      i64 p;
+      bool hit;
+      if (staged) {
+        const i32 q = lower_bound_dev(lds, (i32)0, d, w);
+        hit = q < d && lds[q] == w;
+        p = b + q;
+      } else {
+        p = lower_bound_dev(oadj, b, b + d, w);
+        hit = p < b + d && oadj[p] == w;
+      }
+      if (hit) {
+        atomicAdd(&S[oeid[p]], 1);  // edge (u, w)
+        atomicAdd(&S[oeid[k]], 1);  // edge (v, w)
+        ++c_uv;
       }
     }
+    c_uv = (i32)wave_sum_i64(c_uv);
+    if (lane == 0 && c_uv) atomicAdd(&S[oeid[b + i]], c_uv);  // edge (u, v)
   }
+  __syncthreads();  // the LDS is the next vertex's table
 }
 
 __global__ __launch_bounds__(SUP_THREADS) void k_support(i32 n, const i64* __restrict__ ooff,
@@ -197,7 +223,7 @@ __global__ __launch_bounds__(SUP_THREADS) void k_support(i32 n, const i64* __res
       const i32 d = (i32)(ooff[u + 1] - b);
       if (d < 2) continue;
       if (d > SUP_DMAX) {
-        support_long_row(u, b, d, ooff, oadj, oeid, S);
+        support_long_row(u, b, d, ooff, oadj, oeid, S, keys);
         continue;
       }
       int tbits = 6;
@@ -419,7 +445,7 @@ truss_status build_edges(const Work& w, hipStream_t s) {
 truss_status compute_support(const Work& w, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_i32, dim3(grid_for_h(w.m, 2048)), dim3(PKT_BLOCK), 0, s, w.S, w.m, 0);
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(1), 0, s, &w.ctl->work_queue, (i64)1, 0);
-  hipLaunchKernelGGL(k_support, dim3(1024), dim3(SUP_THREADS), 0, s, n_of(w), (const i64*)w.ooff,
+  hipLaunchKernelGGL(k_support, dim3(SUP_BLOCKS), dim3(SUP_THREADS), 0, s, n_of(w), (const i64*)w.ooff,
                      (const i32*)w.oadj, (const i32*)w.oeid, w.S, &w.ctl->work_queue);
   hipLaunchKernelGGL(k_sum_support, dim3(grid_for_h(w.m, 2048)), dim3(PKT_BLOCK), 0, s, (const i32*)w.S, w.m,
                      w.ctl);

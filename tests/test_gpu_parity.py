@@ -126,6 +126,16 @@ def test_repeatable(gpu_lib):
         assert np.array_equal(gpu_tau(gpu_lib, g), ref)
 
 
+@pytest.mark.parametrize("n", [1100, 2100])
+def test_large_cliques_closed_form(gpu_lib, n):
+    # out-rows longer than the support kernel's LDS hash (1024): staged in LDS up to
+    # 2048 entries, searched in memory beyond; K_n has trussness n and support n - 2
+    g = gg.from_edges(n, itertools.combinations(range(n), 2))
+    say("case K", n)
+    assert np.all(gpu_lib.truss_support(g.offsets, g.adj).cpu().numpy() == n - 2)
+    assert np.all(gpu_tau(gpu_lib, g) == n)
+
+
 def test_empty_and_degenerate(gpu_lib):
     for g in (gg.from_edges(0, []), gg.from_edges(5, []), gg.from_edges(1, [])):
         assert gpu_tau(gpu_lib, g).shape == (0,)
