@@ -246,11 +246,22 @@ __global__ __launch_bounds__(SUP_THREADS) void k_support(i32 n, const i64* __res
         }
       }
       __syncthreads();
-      // one wave per v in N+(u); lanes walk N+(v) and probe the table
+      // one wave per v in N+(u); lanes walk N+(v) and probe the table.  The
+      // wave's next v and the row bounds of the one after are loaded while the
+      // current row is walked (two dependent loads per v, off the critical path).
       const int lane = lane_id(), wid = tid / PKT_WAVE;
-      for (i32 i = wid; i < d; i += SUP_THREADS / PKT_WAVE) {
-        const i32 v = oadj[b + i];
-        const i64 vb = ooff[v], ve = ooff[v + 1];
+      constexpr int NWV = SUP_THREADS / PKT_WAVE;
+      i32 v1 = wid + NWV < d ? oadj[b + wid + NWV] : 0;
+      i64 vb = 0, ve = 0;
+      if (wid < d) {
+        const i32 v0 = oadj[b + wid];
+        vb = ooff[v0];
+        ve = ooff[v0 + 1];
+      }
+      for (i32 i = wid; i < d; i += NWV) {
+        const bool more1 = i + NWV < d, more2 = i + 2 * NWV < d;
+        const i32 v2 = more2 ? oadj[b + i + 2 * NWV] : 0;
+        const i64 vb1 = more1 ? ooff[v1] : 0, ve1 = more1 ? ooff[v1 + 1] : 0;
         i32 c_uv = 0;
         for (i64 k = vb + lane; k < ve; k += PKT_WAVE) {
           const i32 w = oadj[k];
@@ -269,6 +280,9 @@ __global__ __launch_bounds__(SUP_THREADS) void k_support(i32 n, const i64* __res
         }
         c_uv = (i32)wave_sum_i64(c_uv);
         if (lane == 0 && c_uv) atomicAdd(&cnt[i], c_uv);  // edge (u, v)
+        vb = vb1;
+        ve = ve1;
+        v1 = v2;
       }
       __syncthreads();
       for (int i = tid; i < d; i += SUP_THREADS)
