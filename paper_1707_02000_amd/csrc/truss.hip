@@ -263,19 +263,26 @@ __global__ __launch_bounds__(SUP_THREADS) void k_support(i32 n, const i64* __res
         const i32 v2 = more2 ? oadj[b + i + 2 * NWV] : 0;
         const i64 vb1 = more1 ? ooff[v1] : 0, ve1 = more1 ? ooff[v1 + 1] : 0;
         i32 c_uv = 0;
-        for (i64 k = vb + lane; k < ve; k += PKT_WAVE) {
-          const i32 w = oadj[k];
-          u32 h = ((u32)w * 0x9E3779B1u) >> (32 - tbits);
-          for (;;) {
-            const i32 key = keys[h];
-            if (key == w) {
-              atomicAdd(&cnt[slot[h]], 1);  // edge (u, w)
-              atomicAdd(&S[oeid[k]], 1);    // edge (v, w)
-              ++c_uv;
-              break;
+        for (i64 k0 = vb + lane; k0 < ve; k0 += 2 * PKT_WAVE) {  // two entries per lane in flight
+          const i64 k1 = k0 + PKT_WAVE;
+          const i32 w0 = oadj[k0], w1 = k1 < ve ? oadj[k1] : -1;
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const i32 w = q ? w1 : w0;
+            const i64 k = q ? k1 : k0;
+            if (w < 0) continue;
+            u32 h = ((u32)w * 0x9E3779B1u) >> (32 - tbits);
+            for (;;) {
+              const i32 key = keys[h];
+              if (key == w) {
+                atomicAdd(&cnt[slot[h]], 1);  // edge (u, w)
+                atomicAdd(&S[oeid[k]], 1);    // edge (v, w)
+                ++c_uv;
+                break;
+              }
+              if (key == -1) break;
+              h = (h + 1) & (tsize - 1);
             }
-            if (key == -1) break;
-            h = (h + 1) & (tsize - 1);
           }
         }
         c_uv = (i32)wave_sum_i64(c_uv);
