@@ -35,7 +35,8 @@ METRIC = "truss-decomposed edges/s, R-MAT s20/s24; batched+learned vs plain, 1 M
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # Algorithmic bytes of the wide sub-level kernel (one item = one entry of the shorter
 # working row searched in the longer row): the entry's vertex id and edge id (8 B),
-# that edge's state byte (1 B) and the longer-row entry the search lands on (4 B);
+# that edge's state (1 B as a byte; here in its support word) and the longer-row entry
+# the search lands on (4 B);
 # per frontier edge: its id (4 B), endpoints (8 B) and four row offsets (32 B).
 BYTES_PER_ITEM = 13
 BYTES_PER_FRONTIER_EDGE = 44

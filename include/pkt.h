@@ -51,7 +51,9 @@ typedef enum {
   TRUSS_E_ARG = 1,           /* bad argument: NULL pointer, negative size, bad option */
   TRUSS_E_NOT_SIMPLE = 2,    /* a row is not strictly ascending, or has a self-loop */
   TRUSS_E_NOT_SYMMETRIC = 3, /* (u, v) present without (v, u) */
-  TRUSS_E_RANGE = 4,         /* vertex id outside [0, n), bad offsets, or m too large */
+  TRUSS_E_RANGE = 4,         /* vertex id outside [0, n), bad offsets, m too large, or (with more
+                                than 2^28 - 1 edges) a vertex of degree above 2^28, whose edge
+                                supports would not fit the 29-bit support field */
   TRUSS_E_WORKSPACE = 5,     /* workspace too small or misaligned (needs 256-byte alignment) */
   TRUSS_E_DEVICE = 6,        /* a HIP call failed; see truss_last_error() */
   TRUSS_E_INTERNAL = 7       /* iteration bound exceeded (a level or sub-level watchdog) */

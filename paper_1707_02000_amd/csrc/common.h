@@ -17,22 +17,36 @@ typedef uint8_t u8;
 #define PKT_WAVE 64
 #define PKT_BLOCK 256  // 4 waves
 
-// Edge states of the peeling (the paper's inCurr / inNext / processed) as one
-// byte per edge: ST_ALIVE until the edge joins a frontier, then the tag of the
-// round that processes it, three tags in rotation.  During round r an edge is
-// current iff its tag is round_tag(r), joined the next frontier iff round_tag(r +
-// 1), and processed iff ST_PROC or round_tag(r - 1): round r itself turns the
-// round_tag(r - 1) edges (its previous frontier) into ST_PROC, so that tag is
-// free again when round r + 1 hands it to its next frontier.  Ending a round is
-// then a counter update, with no pass between rounds.
+// Edge states of the peeling (the paper's inCurr / inNext / processed): ST_ALIVE
+// until the edge joins a frontier, then the tag of the round that processes it,
+// three tags in rotation.  During round r an edge is current iff its tag is
+// round_tag(r), joined the next frontier iff round_tag(r + 1), and processed iff
+// ST_PROC or round_tag(r - 1): round r itself turns the round_tag(r - 1) edges
+// (its previous frontier) into ST_PROC, so that tag is free again when round
+// r + 1 hands it to its next frontier.  Ending a round is then a counter update,
+// with no pass between rounds.
 enum : u8 { ST_ALIVE = 0, ST_PROC = 1 };
 __host__ __device__ __forceinline__ u8 round_tag(int r) { return (u8)(2 + (unsigned)r % 3u); }
 __host__ __device__ __forceinline__ bool is_processed(u8 st, int r) {
   return st == ST_PROC || st == round_tag(r + 2);
 }
 
+// One 32-bit word per edge holds both its support and its state: the support in
+// the upper 29 bits (two's complement, so the brief undershoot of a decrement
+// that is then undone stays inside the field) and the state in the low 3.  A
+// decrement subtracts SW_ONE and leaves the state bits alone; joining a frontier
+// ORs a round tag into ST_ALIVE (zero) bits; retiring XORs the tag into ST_PROC.
+// One load then answers both "is this edge processed" and "is its support above
+// the level", where two arrays would cost two random lines.
+#define SW_SHIFT 3
+#define SW_ONE (1 << SW_SHIFT)
+#define SW_MAX_SUPPORT ((1 << (31 - SW_SHIFT)) - 1)
+__host__ __device__ __forceinline__ i32 sw_sup(i32 w) { return w >> SW_SHIFT; }
+__host__ __device__ __forceinline__ u8 sw_st(i32 w) { return (u8)(w & (SW_ONE - 1)); }
+__host__ __device__ __forceinline__ i32 sw_make(i32 sup, u8 st) { return (i32)((u32)sup << SW_SHIFT) | st; }
+
 // Validation error bits.
-enum : u32 { VERR_RANGE = 1u, VERR_NOT_SIMPLE = 2u, VERR_NOT_SYMMETRIC = 4u };
+enum : u32 { VERR_RANGE = 1u, VERR_NOT_SIMPLE = 2u, VERR_NOT_SYMMETRIC = 4u, VERR_DEGREE = 8u };
 
 // ---------------------------------------------------------------- host errors
 namespace pkt {

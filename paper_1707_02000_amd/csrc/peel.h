@@ -69,8 +69,7 @@ struct PeelArgs {
   i32* A1;
   const int2* el;
   CsrSet csr;
-  i32* S;
-  u8* state;
+  i32* sw;  // support words (sw_make)
   i32* order;  // truss_options::peel_round, or NULL
   i64 m;  // edges
   i32 alone_frontier, alone_items, alone_alive;  // single-block continuation limits (0: none)
@@ -111,4 +110,5 @@ truss_status compute_support(const Work& w, hipStream_t s);
 truss_status init_peel(const Work& w, hipStream_t s);
 truss_status compact(const Work& w, hipStream_t s);
 truss_status write_output(const Work& w, i32* out, hipStream_t s);
+truss_status write_support(const Work& w, i32* out, hipStream_t s);
 }  // namespace pkt

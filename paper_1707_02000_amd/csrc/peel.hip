@@ -45,46 +45,44 @@ namespace {
 // lower id -- the higher id with owner_higher).  The atomic's old value decides:
 // l + 1 means x now sits at l and joins the next frontier (tag of round r + 1);
 // <= l means the decrement overshot (another thread got there first) and is
-// undone.  The plain pre-read of S may be stale: while S[x] > l every older value
-// is > l too, and once S[x] <= l it stays <= l for the level, so a stale read can
-// only cause a decrement that is then undone.  Whether y is current comes from
-// the caller's earlier read of y's state: during a round a state only changes
-// between values that are not the round's tag (alive -> next, previous round ->
-// processed), so that read answers for the whole round.  The next-frontier tag
-// written here reads as "not current" and "not processed" to every other thread.
+// undone.  The caller's earlier read of x's word may be stale: while the support
+// is > l every older value is > l too, and once it is <= l it stays <= l for the
+// level, so a stale read can only cause a decrement that is then undone.  Whether
+// y is current comes from the same earlier read of y's word: during a round a
+// state only changes between values that are not the round's tag (alive -> next,
+// previous round -> processed), so that read answers for the whole round.  The
+// next-frontier tag written here reads as "not current" and "not processed" to
+// every other thread.
 //
-// Applied to both other edges es, eo of one triangle (states ss, so): (x, y) =
-// (es, eo) and (eo, es), with the two edges' memory operations interleaved --
-// both pre-reads, then both atomics -- so their round trips overlap (different
-// words: their order does not matter).  xa / xb get es / eo if they joined the
-// next frontier, else -1.
-__device__ __forceinline__ void psl_tri(i32 es, u8 ss, i32 eo, u8 so, i32 e1, i32 l, i32 r, i32* S, u8* state,
-                                        i32* order, int owner_higher, i32& xa, i32& xb) {
+// Applied to both other edges es, eo of one triangle (words ws, wo as read by the
+// caller): (x, y) = (es, eo) and (eo, es), both atomics issued before either
+// result is used, so their round trips overlap.  xa / xb get es / eo if they
+// joined the next frontier, else -1.
+__device__ __forceinline__ void psl_tri(i32 es, i32 ws, i32 eo, i32 wo, i32 e1, i32 l, i32 r, i32* sw, i32* order,
+                                        int owner_higher, i32& xa, i32& xb) {
   const u8 tcur = round_tag(r);
-  const bool own_s = so != tcur || (owner_higher ? (e1 > eo) : (e1 < eo));
-  const bool own_o = ss != tcur || (owner_higher ? (e1 > es) : (e1 < es));
-  const i32 vs = own_s ? atomic_load_relaxed(&S[es]) : l;
-  const i32 vo = own_o ? atomic_load_relaxed(&S[eo]) : l;
-  const bool ds = vs > l, dd = vo > l;
-  const i32 as = ds ? atomicSub(&S[es], 1) : 0;
-  const i32 ao = dd ? atomicSub(&S[eo], 1) : 0;
+  const bool own_s = sw_st(wo) != tcur || (owner_higher ? (e1 > eo) : (e1 < eo));
+  const bool own_o = sw_st(ws) != tcur || (owner_higher ? (e1 > es) : (e1 < es));
+  const bool ds = own_s && sw_sup(ws) > l, dd = own_o && sw_sup(wo) > l;
+  const i32 as = ds ? sw_sup(atomicSub(&sw[es], SW_ONE)) : 0;
+  const i32 ao = dd ? sw_sup(atomicSub(&sw[eo], SW_ONE)) : 0;
   xa = xb = -1;
   if (ds) {
     if (as == l + 1) {
-      state[es] = round_tag(r + 1);
+      atomicOr(&sw[es], (i32)round_tag(r + 1));
       if (order) order[es] = r + 1;
       xa = es;
     } else if (as <= l) {
-      atomicAdd(&S[es], 1);
+      atomicAdd(&sw[es], SW_ONE);
     }
   }
   if (dd) {
     if (ao == l + 1) {
-      state[eo] = round_tag(r + 1);
+      atomicOr(&sw[eo], (i32)round_tag(r + 1));
       if (order) order[eo] = r + 1;
       xb = eo;
     } else if (ao <= l) {
-      atomicAdd(&S[eo], 1);
+      atomicAdd(&sw[eo], SW_ONE);
     }
   }
 }
@@ -281,18 +279,18 @@ __device__ __forceinline__ void psl_item_rows(const PeelArgs& a, const Csr& c, i
   i64 p = r.lb;
   for (i64 j = j0; j < j1; ++j) {
     const i32 es = c.eid[j];
-    const u8 ss = a.state[es];
-    if (is_processed(ss, rd)) continue;
+    const i32 ws = a.sw[es];
+    if (is_processed(sw_st(ws), rd)) continue;
     const i32 w = c.adj[j];
     p = (j == j0) ? lower_bound_dev(c.adj, p, r.le, w) : gallop(c.adj, p, r.le, w);
     if (p == r.le) break;
     if (c.adj[p] != w) continue;
     const i32 eo = c.eid[p];
     ++p;
-    const u8 so = a.state[eo];
-    if (is_processed(so, rd)) continue;
+    const i32 wo = a.sw[eo];
+    if (is_processed(sw_st(wo), rd)) continue;
     i32 y[2];
-    psl_tri(es, ss, eo, so, e1, l, rd, a.S, a.state, a.order, a.owner_higher, y[0], y[1]);
+    psl_tri(es, ws, eo, wo, e1, l, rd, a.sw, a.order, a.owner_higher, y[0], y[1]);
     for (int q = 0; q < 2; ++q) {
       if (y[q] < 0) continue;
       if (x0 < 0)
@@ -398,8 +396,7 @@ __device__ void scan_tiles(const PeelArgs& a, i32 l, i32 r, i32 na, const i32* _
   for (i64 t0 = tile0 * tile; t0 < na; t0 += tstride * tile) {
     u32 tk = 0, kp = 0;
     i32 ev[SCAN_ITEMS];
-    u8 st[SCAN_ITEMS];
-    i32 sv[SCAN_ITEMS];
+    i32 wv[SCAN_ITEMS];
     // all loads first (no branch between them), then classify
 #pragma unroll
     for (int k = 0; k < SCAN_ITEMS; ++k) {
@@ -407,19 +404,15 @@ __device__ void scan_tiles(const PeelArgs& a, i32 l, i32 r, i32 na, const i32* _
       ev[k] = (i < na) ? A[i] : -1;
     }
 #pragma unroll
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-      const i32 e = ev[k] < 0 ? 0 : ev[k];
-      st[k] = a.state[e];
-      sv[k] = a.S[e];
-    }
+    for (int k = 0; k < SCAN_ITEMS; ++k) wv[k] = a.sw[ev[k] < 0 ? 0 : ev[k]];
 #pragma unroll
     for (int k = 0; k < SCAN_ITEMS; ++k) {
-      if (ev[k] >= 0 && st[k] == ST_ALIVE) {
-        if (sv[k] == l) {
+      if (ev[k] >= 0 && sw_st(wv[k]) == ST_ALIVE) {
+        if (sw_sup(wv[k]) == l) {
           tk |= 1u << k;
         } else {
           kp |= 1u << k;
-          mn = min(mn, sv[k]);
+          mn = min(mn, sw_sup(wv[k]));
         }
       }
     }
@@ -434,7 +427,7 @@ __device__ void scan_tiles(const PeelArgs& a, i32 l, i32 r, i32 na, const i32* _
     for (int k = 0; k < SCAN_ITEMS; ++k) {
       if ((tk >> k) & 1u) {
         curr[sbase[0] + pt[k]] = ev[k];
-        a.state[ev[k]] = round_tag(r);
+        a.sw[ev[k]] = sw_make(l, round_tag(r));  // alive at l: nothing else writes it during a scan
         if (a.order) a.order[ev[k]] = r;
       } else if ((kp >> k) & 1u) {
         Aout[sbase[1] + pk[k]] = ev[k];
@@ -446,9 +439,10 @@ __device__ void scan_tiles(const PeelArgs& a, i32 l, i32 r, i32 na, const i32* _
 
 // The previous round's frontier turns processed (its tag is handed out again by
 // the next round); every block of a round takes a strided share.
-__device__ __forceinline__ void mark_prev(const PeelArgs& a, int sel, i32 nprev, i64 tid, i64 stride) {
+__device__ __forceinline__ void mark_prev(const PeelArgs& a, int sel, i32 r, i32 nprev, i64 tid, i64 stride) {
   const i32* prev = prev_of(a, sel);
-  for (i64 i = tid; i < nprev; i += stride) a.state[prev[i]] = ST_PROC;
+  const i32 flip = (i32)(round_tag(r + 2) ^ ST_PROC);
+  for (i64 i = tid; i < nprev; i += stride) atomicXor(&a.sw[prev[i]], flip);
 }
 
 // Rows of the frontier edges of a fused round, kept in LDS so that an item
@@ -624,7 +618,7 @@ __device__ void go_alone(const PeelArgs& a, AloneLds<NT>& s) {
     i32* next = next_of(a, sel);
     const i64 total = lds_work_prefix<NT>(a, c, curr, s.v.ncurr, l, s.v.variant, s.P, s.tmp);
     if (total > a.alone_items) break;
-    mark_prev(a, sel, s.v.nprev, threadIdx.x, NT);
+    mark_prev(a, sel, r, s.v.nprev, threadIdx.x, NT);
     lds_items<NT>(a, c, curr, s.v.ncurr, l, r, s.v.variant, s.P, total, 0, NT, next);
     __syncthreads();  // every wave's appends are counted before the count is read
     if (threadIdx.x == 0) ctl_after_sublevel(ctl, s.v.ncurr, atomicAdd(&ctl->nnext, 0), sel);
@@ -668,28 +662,23 @@ __device__ __forceinline__ void scan_chunk(i32 na, int G, i64* c0, i64* c1) {
 // kept.
 __device__ __forceinline__ void classify(const PeelArgs& a, i32 l, const i32* __restrict__ A, i64 t0, i64 end,
                                          i32* ev, u32& tk, u32& kp, i32& mn) {
-  u8 st[SCAN_ITEMS];
-  i32 sv[SCAN_ITEMS];
+  i32 wv[SCAN_ITEMS];
 #pragma unroll
   for (int k = 0; k < SCAN_ITEMS; ++k) {
     const i64 i = t0 + (i64)k * PKT_BLOCK + threadIdx.x;
     ev[k] = (i < end) ? A[i] : -1;
   }
 #pragma unroll
-  for (int k = 0; k < SCAN_ITEMS; ++k) {
-    const i32 e = ev[k] < 0 ? 0 : ev[k];
-    st[k] = a.state[e];
-    sv[k] = a.S[e];
-  }
+  for (int k = 0; k < SCAN_ITEMS; ++k) wv[k] = a.sw[ev[k] < 0 ? 0 : ev[k]];
   tk = kp = 0;
 #pragma unroll
   for (int k = 0; k < SCAN_ITEMS; ++k) {
-    if (ev[k] >= 0 && st[k] == ST_ALIVE) {
-      if (sv[k] == l) {
+    if (ev[k] >= 0 && sw_st(wv[k]) == ST_ALIVE) {
+      if (sw_sup(wv[k]) == l) {
         tk |= 1u << k;
       } else {
         kp |= 1u << k;
-        mn = min(mn, sv[k]);
+        mn = min(mn, sw_sup(wv[k]));
       }
     }
   }
@@ -784,7 +773,7 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_scan_write(PeelArgs a, const i64*
     for (int k = 0; k < SCAN_ITEMS; ++k) {
       if ((tk >> k) & 1u) {
         curr[bt + pt[k]] = ev[k];
-        a.state[ev[k]] = round_tag(r);
+        a.sw[ev[k]] = sw_make(l, round_tag(r));  // alive at l: nothing else writes it during a scan
         if (a.order) a.order[ev[k]] = r;
       } else if ((kp >> k) & 1u) {
         Aout[bk + pk[k]] = ev[k];
@@ -821,7 +810,7 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_psl_small(PeelArgs a) {
   const i32* curr = cur_of(a, sel);
   i32* next = next_of(a, sel);
   if (blockIdx.x == 0 && threadIdx.x == 0) ctl->round_done = 1;
-  mark_prev(a, sel, v.nprev, (i64)blockIdx.x * SMALL_THREADS + threadIdx.x, (i64)nblk * SMALL_THREADS);
+  mark_prev(a, sel, v.r, v.nprev, (i64)blockIdx.x * SMALL_THREADS + threadIdx.x, (i64)nblk * SMALL_THREADS);
   const i64 total = lds_work_prefix<SMALL_THREADS>(a, c, curr, nc, l, v.variant, P, tmp, &er);
   lds_items<SMALL_THREADS>(a, c, curr, nc, l, r, v.variant, P, total, (i64)blockIdx.x * SMALL_THREADS,
                            (i64)nblk * SMALL_THREADS, next, &er);
@@ -904,9 +893,9 @@ __device__ void tile_one_edge(const PeelArgs& a, const Csr& c, const i32* curr, 
     }
     if (p >= 0) {
       const i32 es = c.eid[j], eo = c.eid[p];
-      const u8 ss = a.state[es], so = a.state[eo];
-      if (!is_processed(ss, r) && !is_processed(so, r)) {
-        psl_tri(es, ss, eo, so, te.e1, l, r, a.S, a.state, a.order, a.owner_higher, x0, x1);
+      const i32 ws = a.sw[es], wo = a.sw[eo];
+      if (!is_processed(sw_st(ws), r) && !is_processed(sw_st(wo), r)) {
+        psl_tri(es, ws, eo, wo, te.e1, l, r, a.sw, a.order, a.owner_higher, x0, x1);
       }
     }
   }
@@ -940,7 +929,7 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_psl_bsearch(PeelArgs a, const i64
   const i32* curr = cur_of(a, sel);
   i32* next = next_of(a, sel);
   const Csr c = a.csr.pick(v.csel);
-  mark_prev(a, sel, v.nprev, (i64)blockIdx.x * PKT_BLOCK + threadIdx.x, (i64)nblk * PKT_BLOCK);
+  mark_prev(a, sel, v.r, v.nprev, (i64)blockIdx.x * PKT_BLOCK + threadIdx.x, (i64)nblk * PKT_BLOCK);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ctl->round_done = 1;
     if (total > 0) {  // accounting for the roofline report
@@ -1091,8 +1080,7 @@ PeelArgs peel_args(const Work& w, const truss_options& opt) {
   a.A1 = w.A[1];
   a.el = w.el;
   a.csr = csr_set(w);
-  a.S = w.S;
-  a.state = w.state;
+  a.sw = w.sw;
   a.order = opt.peel_round;
   a.m = w.m;
   // The single-block continuation saves host round trips; with launch sequences
@@ -1346,7 +1334,8 @@ truss_status run_single(const Work& w, const truss_options& opt, truss_stats* st
   if (st) return st;
   tm.mark();  // 3
   if (support_only) {
-    PKT_HIP(hipMemcpyAsync(trussness, w.S, (size_t)w.m * sizeof(i32), hipMemcpyDeviceToDevice, s));
+    st = write_support(w, trussness, s);
+    if (st) return st;
     PKT_HIP(hipStreamSynchronize(s));
     return TRUSS_OK;
   }

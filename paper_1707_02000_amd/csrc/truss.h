@@ -73,8 +73,7 @@ struct Work {
   i64* ebase;       // [n+1] first edge id of each row (exclusive scan of upper counts)
   i32* eid;         // [2m] edge id per adjacency slot
   int2* el;         // [m] endpoints (u < v)
-  i32* S;           // [m] support
-  u8* state;        // [m] edge state (ST_ALIVE, ST_PROC or a round tag)
+  i32* sw;          // [m] support word: support and edge state (sw_make)
   i32* F[3];        // [m] frontiers: current, next, previous (rotating)
   i32* A[2];        // [m] alive lists
   i64* coff[2];     // [n+1] compacted offsets

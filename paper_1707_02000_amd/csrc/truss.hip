@@ -79,13 +79,16 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_validate(i32 n, const i64* __rest
 
 // ------------------------------------------------------------ edge ids etc.
 
-// Per row: degree, neighbours below the vertex, and the count above it.
+// Per row: degree, neighbours below the vertex, and the count above it.  A degree
+// whose edges could hold a support past SW_MAX_SUPPORT sets VERR_DEGREE.
 __global__ __launch_bounds__(PKT_BLOCK) void k_rowinfo(i32 n, const i64* __restrict__ off,
                                                       const i32* __restrict__ adj, i32* __restrict__ deg,
-                                                      i32* __restrict__ locnt, i32* __restrict__ upcnt) {
+                                                      i32* __restrict__ locnt, i32* __restrict__ upcnt,
+                                                      u32* __restrict__ verr) {
   for (i64 u = (i64)blockIdx.x * PKT_BLOCK + threadIdx.x; u < n; u += (i64)gridDim.x * PKT_BLOCK) {
     const i64 b = off[u], e = off[u + 1];
     const i64 lo = lower_bound_dev(adj, b, e, (i32)u) - b;
+    if (e - b > (i64)SW_MAX_SUPPORT + 1) atomicOr(verr, VERR_DEGREE);  // support <= degree - 1
     deg[u] = (i32)(e - b);
     locnt[u] = (i32)lo;
     upcnt[u] = (i32)(e - b - lo);
@@ -168,7 +171,7 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_orient(i32 n, i64 two_m, const i6
 // hash table's space) when it fits in 2 * SUP_DMAX entries, else in memory; all
 // three edges by global atomics.
 __device__ void support_long_row(i32 b_u, i64 b, i32 d, const i64* __restrict__ ooff, const i32* __restrict__ oadj,
-                                 const i32* __restrict__ oeid, i32* __restrict__ S, i32* lds) {
+                                 const i32* __restrict__ oeid, i32* __restrict__ sw, i32* lds) {
   const bool staged = d <= 2 * SUP_DMAX;
   if (staged) {
     for (int i = threadIdx.x; i < d; i += SUP_THREADS) lds[i] = oadj[b + i];
@@ -192,20 +195,20 @@ __device__ void support_long_row(i32 b_u, i64 b, i32 d, const i64* __restrict__ 
         hit = p < b + d && oadj[p] == w;
       }
       if (hit) {
-        atomicAdd(&S[oeid[p]], 1);  // edge (u, w)
-        atomicAdd(&S[oeid[k]], 1);  // edge (v, w)
+        atomicAdd(&sw[oeid[p]], SW_ONE);  // edge (u, w)
+        atomicAdd(&sw[oeid[k]], SW_ONE);  // edge (v, w)
         ++c_uv;
       }
     }
     c_uv = (i32)wave_sum_i64(c_uv);
-    if (lane == 0 && c_uv) atomicAdd(&S[oeid[b + i]], c_uv);  // edge (u, v)
+    if (lane == 0 && c_uv) atomicAdd(&sw[oeid[b + i]], c_uv * SW_ONE);  // edge (u, v)
   }
   __syncthreads();  // the LDS is the next vertex's table
 }
 
 __global__ __launch_bounds__(SUP_THREADS) void k_support(i32 n, const i64* __restrict__ ooff,
                                                         const i32* __restrict__ oadj, const i32* __restrict__ oeid,
-                                                        i32* __restrict__ S, i32* __restrict__ queue) {
+                                                        i32* __restrict__ sw, i32* __restrict__ queue) {
   __shared__ i32 keys[SUP_TBL];
   __shared__ unsigned short slot[SUP_TBL];
   __shared__ i32 cnt[SUP_DMAX];
@@ -223,7 +226,7 @@ __global__ __launch_bounds__(SUP_THREADS) void k_support(i32 n, const i64* __res
       const i32 d = (i32)(ooff[u + 1] - b);
       if (d < 2) continue;
       if (d > SUP_DMAX) {
-        support_long_row(u, b, d, ooff, oadj, oeid, S, keys);
+        support_long_row(u, b, d, ooff, oadj, oeid, sw, keys);
         continue;
       }
       int tbits = 6;
@@ -276,7 +279,7 @@ __global__ __launch_bounds__(SUP_THREADS) void k_support(i32 n, const i64* __res
               const i32 key = keys[h];
               if (key == w) {
                 atomicAdd(&cnt[slot[h]], 1);  // edge (u, w)
-                atomicAdd(&S[oeid[k]], 1);    // edge (v, w)
+                atomicAdd(&sw[oeid[k]], SW_ONE);  // edge (v, w)
                 ++c_uv;
                 break;
               }
@@ -293,14 +296,10 @@ __global__ __launch_bounds__(SUP_THREADS) void k_support(i32 n, const i64* __res
       }
       __syncthreads();
       for (int i = tid; i < d; i += SUP_THREADS)
-        if (cnt[i]) atomicAdd(&S[oeid[b + i]], cnt[i]);
+        if (cnt[i]) atomicAdd(&sw[oeid[b + i]], cnt[i] * SW_ONE);
       __syncthreads();
     }
   }
-}
-
-__global__ __launch_bounds__(PKT_BLOCK) void k_fill_u8(u8* __restrict__ a, i64 n, u8 v) {
-  for (i64 i = (i64)blockIdx.x * PKT_BLOCK + threadIdx.x; i < n; i += (i64)gridDim.x * PKT_BLOCK) a[i] = v;
 }
 
 __global__ __launch_bounds__(PKT_BLOCK) void k_fill_i32(i32* __restrict__ a, i64 n, i32 v) {
@@ -312,9 +311,9 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_iota(i32* __restrict__ a, i64 n) 
 }
 
 // Sum of supports (3 x triangles) into ctl->tri3.
-__global__ __launch_bounds__(PKT_BLOCK) void k_sum_support(const i32* __restrict__ S, i64 m, Ctl* ctl) {
+__global__ __launch_bounds__(PKT_BLOCK) void k_sum_support(const i32* __restrict__ sw, i64 m, Ctl* ctl) {
   i64 s = 0;
-  for (i64 i = (i64)blockIdx.x * PKT_BLOCK + threadIdx.x; i < m; i += (i64)gridDim.x * PKT_BLOCK) s += S[i];
+  for (i64 i = (i64)blockIdx.x * PKT_BLOCK + threadIdx.x; i < m; i += (i64)gridDim.x * PKT_BLOCK) s += sw_sup(sw[i]);
   s = wave_sum_i64(s);
   if (lane_id() == 0 && s) atomicAdd((unsigned long long*)&ctl->tri3, (unsigned long long)s);
 }
@@ -328,11 +327,11 @@ struct KeepLen {
   __device__ i64 len(i64 i) const { return flag[i]; }
 };
 
-__global__ __launch_bounds__(PKT_BLOCK) void k_keep_flags(Csr c, i64 slots, const u8* __restrict__ state,
+__global__ __launch_bounds__(PKT_BLOCK) void k_keep_flags(Csr c, i64 slots, const i32* __restrict__ sw,
                                                          const Ctl* __restrict__ ctl, u8* __restrict__ flag) {
   const i32 r = ctl->sublevels;  // between rounds: the next round's index
   for (i64 j = (i64)blockIdx.x * PKT_BLOCK + threadIdx.x; j < slots; j += (i64)gridDim.x * PKT_BLOCK)
-    flag[j] = !is_processed(state[c.eid[j]], r);
+    flag[j] = !is_processed(sw_st(sw[c.eid[j]]), r);
 }
 
 __global__ __launch_bounds__(PKT_BLOCK) void k_compact(i32 n, Csr c, i64 slots, const u8* __restrict__ flag,
@@ -356,16 +355,22 @@ __global__ void k_after_compact(Ctl* ctl, i32 dst, i32 m) {
 }
 
 // trussness = final support + 2 (Algorithm 1's last step; Algorithm 4 output).
-__global__ __launch_bounds__(PKT_BLOCK) void k_output(const i32* __restrict__ S, i64 m, i32* __restrict__ out,
+__global__ __launch_bounds__(PKT_BLOCK) void k_output(const i32* __restrict__ sw, i64 m, i32* __restrict__ out,
                                                      Ctl* ctl) {
   i32 mx = 0;
   for (i64 i = (i64)blockIdx.x * PKT_BLOCK + threadIdx.x; i < m; i += (i64)gridDim.x * PKT_BLOCK) {
-    const i32 s = S[i];
-    out[i] = s + 2;
-    mx = max(mx, s + 2);
+    const i32 t = sw_sup(sw[i]) + 2;
+    out[i] = t;
+    mx = max(mx, t);
   }
   mx = wave_max_i32(mx);
   if (lane_id() == 0) atomicMax(&ctl->tmax_s, mx);
+}
+
+// Support alone (no peeling): the support field of every word.
+__global__ __launch_bounds__(PKT_BLOCK) void k_support_out(const i32* __restrict__ sw, i64 m, i32* __restrict__ out) {
+  for (i64 i = (i64)blockIdx.x * PKT_BLOCK + threadIdx.x; i < m; i += (i64)gridDim.x * PKT_BLOCK)
+    out[i] = sw_sup(sw[i]);
 }
 
 __global__ void k_off32_to_64(const i32* __restrict__ a, i64* __restrict__ b, i64 n) {
@@ -395,8 +400,7 @@ size_t work_layout(i32 n, i64 two_m, bool off32, void* base, Work* w) {
   t.ebase = cv.take<i64>((size_t)n + 1);
   t.eid = cv.take<i32>((size_t)two_m);
   t.el = cv.take<int2>((size_t)m);
-  t.S = cv.take<i32>((size_t)m);
-  t.state = cv.take<u8>((size_t)m);
+  t.sw = cv.take<i32>((size_t)m);
   for (int k = 0; k < 3; ++k) t.F[k] = cv.take<i32>((size_t)m);
   for (int k = 0; k < 2; ++k) t.A[k] = cv.take<i32>((size_t)m);
   for (int k = 0; k < 2; ++k) {
@@ -451,8 +455,23 @@ truss_status validate_input(const Work& w, hipStream_t s) {
 // Edge ids, endpoint list and oriented CSR.
 truss_status build_edges(const Work& w, hipStream_t s) {
   const i32 n = w.n;
+  // Only a graph of more than SW_MAX_SUPPORT edges can hold an edge of larger
+  // support (s triangles on one edge take 2 s + 1 edges); only then is the degree
+  // check read back.
+  const bool big = w.m > (i64)SW_MAX_SUPPORT;
+  if (big) PKT_HIP(hipMemsetAsync(w.verr, 0, sizeof(u32), s));
   hipLaunchKernelGGL(k_rowinfo, dim3(grid_for_h(n)), dim3(PKT_BLOCK), 0, s, n, w.off, w.adj, w.deg, w.locnt,
-                     w.upcnt);
+                     w.upcnt, w.verr);
+  if (big) {
+    u32 bits = 0;
+    PKT_HIP(hipMemcpyAsync(&bits, w.verr, sizeof(u32), hipMemcpyDeviceToHost, s));
+    PKT_HIP(hipStreamSynchronize(s));
+    if (bits & VERR_DEGREE) {
+      set_error("a vertex has degree above %d: its supports would not fit the 29-bit support field",
+                SW_MAX_SUPPORT + 1);
+      return TRUSS_E_RANGE;
+    }
+  }
   PKT_HIP(scan_launch(ArrayLen<i32>{(const i32*)w.upcnt, n}, w.partial, w.ebase, &w.ctl->scan_arrive, s));
   hipLaunchKernelGGL(k_slots, dim3(grid_for_h(w.two_m)), dim3(PKT_BLOCK), 0, s, n, w.two_m, w.off, w.adj, w.deg,
                      w.locnt, w.ebase, w.eid, w.el, w.flag);
@@ -464,18 +483,18 @@ truss_status build_edges(const Work& w, hipStream_t s) {
 }
 
 truss_status compute_support(const Work& w, hipStream_t s) {
-  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for_h(w.m, 2048)), dim3(PKT_BLOCK), 0, s, w.S, w.m, 0);
+  // support 0, state ST_ALIVE
+  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for_h(w.m, 2048)), dim3(PKT_BLOCK), 0, s, w.sw, w.m, sw_make(0, ST_ALIVE));
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(1), 0, s, &w.ctl->work_queue, (i64)1, 0);
   hipLaunchKernelGGL(k_support, dim3(SUP_BLOCKS), dim3(SUP_THREADS), 0, s, n_of(w), (const i64*)w.ooff,
-                     (const i32*)w.oadj, (const i32*)w.oeid, w.S, &w.ctl->work_queue);
-  hipLaunchKernelGGL(k_sum_support, dim3(grid_for_h(w.m, 2048)), dim3(PKT_BLOCK), 0, s, (const i32*)w.S, w.m,
+                     (const i32*)w.oadj, (const i32*)w.oeid, w.sw, &w.ctl->work_queue);
+  hipLaunchKernelGGL(k_sum_support, dim3(grid_for_h(w.m, 2048)), dim3(PKT_BLOCK), 0, s, (const i32*)w.sw, w.m,
                      w.ctl);
   PKT_LAUNCH_CHECK();
   return TRUSS_OK;
 }
 
 truss_status init_peel(const Work& w, hipStream_t s) {
-  hipLaunchKernelGGL(k_fill_u8, dim3(grid_for_h(w.m, 2048)), dim3(PKT_BLOCK), 0, s, w.state, w.m, (u8)ST_ALIVE);
   hipLaunchKernelGGL(k_iota, dim3(grid_for_h(w.m, 2048)), dim3(PKT_BLOCK), 0, s, w.A[0], w.m);
   PKT_LAUNCH_CHECK();
   return TRUSS_OK;
@@ -501,7 +520,7 @@ truss_status compact(const Work& w, hipStream_t s) {
   PKT_HIP(hipMemcpyAsync(&slots, cur.off + w.n, sizeof(i64), hipMemcpyDeviceToHost, s));
   PKT_HIP(hipStreamSynchronize(s));
   hipLaunchKernelGGL(k_keep_flags, dim3(grid_for_h(slots)), dim3(PKT_BLOCK), 0, s, cur, slots,
-                     (const u8*)w.state, (const Ctl*)w.ctl, w.flag);
+                     (const i32*)w.sw, (const Ctl*)w.ctl, w.flag);
   PKT_HIP(scan_launch(KeepLen{w.flag, slots}, w.partial, w.X, &w.ctl->scan_arrive, s));
   hipLaunchKernelGGL(k_compact, dim3(grid_for_h(slots)), dim3(PKT_BLOCK), 0, s, w.n, cur, slots,
                      (const u8*)w.flag, (const i64*)w.X, w.coff[dst - 1], w.cadj[dst - 1], w.ceid[dst - 1]);
@@ -511,8 +530,14 @@ truss_status compact(const Work& w, hipStream_t s) {
 }
 
 truss_status write_output(const Work& w, i32* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_output, dim3(grid_for_h(w.m, 2048)), dim3(PKT_BLOCK), 0, s, (const i32*)w.S, w.m, out,
+  hipLaunchKernelGGL(k_output, dim3(grid_for_h(w.m, 2048)), dim3(PKT_BLOCK), 0, s, (const i32*)w.sw, w.m, out,
                      w.ctl);
+  PKT_LAUNCH_CHECK();
+  return TRUSS_OK;
+}
+
+truss_status write_support(const Work& w, i32* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_support_out, dim3(grid_for_h(w.m, 2048)), dim3(PKT_BLOCK), 0, s, (const i32*)w.sw, w.m, out);
   PKT_LAUNCH_CHECK();
   return TRUSS_OK;
 }
