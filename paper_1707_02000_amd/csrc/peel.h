@@ -26,6 +26,17 @@
 #ifndef ALONE_ITEMS
 #define ALONE_ITEMS 2048      // with at most this many intersection items,
 #endif
+// The working CSR is rebuilt without its processed edges once the edges left
+// are under COMPACT_NUM / COMPACT_DEN of the edges it holds (7/8 measured best
+// on R-MAT scale 22 among 1/2 .. 31/32: stale entries cost every later round's
+// items more than the rebuilds; 3/4 ties it at scale 20).
+#ifndef COMPACT_NUM
+#define COMPACT_NUM 7
+#define COMPACT_DEN 8
+#endif
+__host__ __device__ __forceinline__ bool needs_compact(i64 alive, i64 csr_edges) {
+  return alive * COMPACT_DEN < csr_edges * COMPACT_NUM;
+}
 #ifndef ALONE_ALIVE
 #define ALONE_ALIVE 32768     // and scans alone when the alive list is at most this long
 #endif

@@ -566,7 +566,7 @@ namespace {
 // stores into the host-mapped slot of sequence seq.
 __device__ __forceinline__ void publish_snap(const PeelArgs& a, const Ctl* ctl, LoopSnap* snap, i64 seq) {
   LoopSnap* slot = snap + (seq & (LOOP_SNAP_SLOTS - 1));
-  const i32 compact = (a.m - ctl->processed) * 2 < (i64)ctl->csr_edges;
+  const i32 compact = needs_compact(a.m - ctl->processed, ctl->csr_edges);
   __hip_atomic_store(&slot->w0, snap_w0(seq, ctl->ncurr, ctl->choice, ctl->done, compact), __ATOMIC_RELAXED,
                      __HIP_MEMORY_SCOPE_SYSTEM);
   __hip_atomic_store(&slot->w1, snap_w1(seq, ctl->nalive), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -837,7 +837,9 @@ struct WideLen {
 // NSAMP long, as for most of the work on skewed graphs); a lane finds the bracket of its entry among the samples in LDS and
 // binary-searches only that bracket, at most `step` contiguous entries, in
 // memory.  Consecutive tiles of one edge keep the staged samples.
+#ifndef NSAMP
 #define NSAMP 4096
+#endif
 
 struct TileEdge {
   i64 i0;            // frontier index of the staged edge (-1: none)
@@ -1255,7 +1257,7 @@ inline LoopState state_of(const Ctl& c, i64 m) {
   x.choice = c.choice;
   x.done = c.done;
   x.nalive = c.nalive;
-  x.compact = (m - c.processed) * 2 < (i64)c.csr_edges;
+  x.compact = needs_compact(m - c.processed, c.csr_edges);
   return x;
 }
 
@@ -1354,10 +1356,10 @@ truss_status run_single(const Work& w, const truss_options& opt, truss_stats* st
   if (st) return st;
   i64 guard = 0;
   const i64 guard_max = 4 * w.m + 4096;  // bound on launch sequences / steps
-  // Working-CSR rebuild when under half of its edges are left.  Valid between
+  // Working-CSR rebuild when few of its edges are left (needs_compact).  Valid between
   // any two rounds: rows lose only processed edges, which every round skips.
   auto maybe_compact = [&]() -> truss_status {
-    if (!opt.compact || (i64)(w.m - hc.processed) * 2 >= (i64)hc.csr_edges) return TRUSS_OK;
+    if (!opt.compact || !needs_compact(w.m - hc.processed, hc.csr_edges)) return TRUSS_OK;
     truss_status r = compact(w, s);
     if (r) return r;
     return read_ctl(w, &hc, s);
