@@ -841,6 +841,44 @@ struct WideLen {
 #define NSAMP 4096
 #endif
 
+// Next-frontier appends of one block, gathered in LDS and written out once at
+// the end of the block's tiles with a single reservation on the global counter
+// (every wave of the grid appending to that one counter would queue its atomics
+// at one address, on each tile's critical path).  Entries past the buffer go
+// straight to the global list.
+#define APPEND_LDS 512
+struct BlockAppend {
+  i32 buf[APPEND_LDS];
+  i32 n, base;
+  __device__ __forceinline__ void add1(i32 x, i32* next, i32* counter) {
+    const u64 mask = __ballot(x >= 0);
+    if (mask == 0) return;
+    const int lane = lane_id(), leader = __ffsll((unsigned long long)mask) - 1;
+    i32 b = 0;
+    if (lane == leader) b = atomicAdd(&n, (i32)__popcll(mask));
+    b = __shfl(b, leader);
+    if (x >= 0) {
+      const i32 slot = b + (i32)__popcll(mask & ((1ull << lane) - 1ull));
+      if (slot < APPEND_LDS)
+        buf[slot] = x;
+      else
+        next[atomicAdd(counter, 1)] = x;
+    }
+  }
+  __device__ __forceinline__ void add(i32 x0, i32 x1, i32* next, i32* counter) {
+    add1(x0, next, counter);
+    add1(x1, next, counter);
+  }
+  // Every thread of the block, after its last add.
+  __device__ __forceinline__ void flush(i32* next, i32* counter) {
+    __syncthreads();
+    const i32 k = min(n, (i32)APPEND_LDS);
+    if (threadIdx.x == 0 && k > 0) base = atomicAdd(counter, k);
+    __syncthreads();
+    for (i32 t = threadIdx.x; t < k; t += PKT_BLOCK) next[base + t] = buf[t];
+  }
+};
+
 struct TileEdge {
   i64 i0;            // frontier index of the staged edge (-1: none)
   i64 sb, lb, step;  // shorter-row start, longer-row start, sample spacing
@@ -848,7 +886,8 @@ struct TileEdge {
 };
 
 __device__ void tile_one_edge(const PeelArgs& a, const Csr& c, const i32* curr, const i64* __restrict__ P, i64 i0,
-                              i64 base, i64 total, i32 l, i32 r, i32* next, TileEdge& te, i32* samp) {
+                              i64 base, i64 total, i32 l, i32 r, i32* next, TileEdge& te, i32* samp,
+                              BlockAppend& ba) {
   if (te.i0 != i0) {  // block-uniform
     __syncthreads();  // the previous tile's lanes are done with samp
     if (threadIdx.x == 0) {
@@ -901,7 +940,7 @@ __device__ void tile_one_edge(const PeelArgs& a, const Csr& c, const i32* curr, 
       }
     }
   }
-  append_next(x0, x1, next, &a.ctl->nnext);
+  ba.add(x0, x1, next, &a.ctl->nnext);
 }
 
 // Wide round: one thread per intersection item over the whole grid, items
@@ -920,6 +959,7 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_psl_bsearch(PeelArgs a, const i64
   __shared__ i64 sp[2];
   __shared__ TileEdge te;
   __shared__ i32 samp[NSAMP];
+  __shared__ BlockAppend ba;
   load_view(ctl, &v);
   if (v.done || v.ncurr == 0 || !is_wide(v.choice)) return;
   const int nblk = v.choice == TRUSS_CHOICE_WIDE_NARROW ? min((int)gridDim.x, WIDE_NARROW_BLOCKS) : gridDim.x;
@@ -940,7 +980,10 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_psl_bsearch(PeelArgs a, const i64
       ctl->wide_launches += 1;
     }
   }
-  if (threadIdx.x == 0) te.i0 = -1;
+  if (threadIdx.x == 0) {
+    te.i0 = -1;
+    ba.n = 0;
+  }
   const i64 tiles = (total + PKT_BLOCK - 1) / PKT_BLOCK;
   const i64 per = (tiles + nblk - 1) / nblk;
   const i64 t_end = min(tiles, ((i64)blockIdx.x + 1) * per);
@@ -952,7 +995,7 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_psl_bsearch(PeelArgs a, const i64
     __syncthreads();
     const i64 s0 = sp[0], s1 = sp[1];
     if (s0 == s1 && variant == TRUSS_VARIANT_BSEARCH) {
-      tile_one_edge(a, c, curr, P, s0, base, total, l, r, next, te, samp);
+      tile_one_edge(a, c, curr, P, s0, base, total, l, r, next, te, samp, ba);
     } else {
       const i64 g = base + threadIdx.x;
       i32 x0 = -1, x1 = -1;
@@ -960,10 +1003,11 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_psl_bsearch(PeelArgs a, const i64
         const i64 i = upper_bound_dev(P, s0, s1 + 1, g) - 1;
         psl_item(a, c, curr[i], g - P[i], l, r, variant, x0, x1, next, &ctl->nnext);
       }
-      append_next(x0, x1, next, &ctl->nnext);
+      ba.add(x0, x1, next, &ctl->nnext);
     }
     __syncthreads();
   }
+  ba.flush(next, &ctl->nnext);
 }
 
 // One block after a level scan or a round: ends the round the previous launch
