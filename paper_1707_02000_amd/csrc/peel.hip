@@ -494,11 +494,48 @@ __device__ i64 lds_work_prefix(const PeelArgs& a, const Csr& c, const i32* curr,
   return tot;
 }
 
+// Next-frontier appends of one block, gathered in LDS and written out once at
+// the end of the block's tiles with a single reservation on the global counter
+// (every wave of the grid appending to that one counter would queue its atomics
+// at one address, on each tile's critical path).  Entries past the buffer go
+// straight to the global list, one reservation per wave.
+#define APPEND_LDS 512
+struct BlockAppend {
+  i32 buf[APPEND_LDS];
+  i32 n, base;
+  __device__ __forceinline__ void add1(i32 x, i32* next, i32* counter) {
+    const u64 mask = __ballot(x >= 0);
+    if (mask == 0) return;
+    const int lane = lane_id(), leader = __ffsll((unsigned long long)mask) - 1;
+    i32 b = 0;
+    if (lane == leader) b = atomicAdd(&n, (i32)__popcll(mask));
+    b = __shfl(b, leader);
+    const i32 slot = b + (i32)__popcll(mask & ((1ull << lane) - 1ull));
+    const bool spill = x >= 0 && slot >= APPEND_LDS;
+    if (x >= 0 && !spill) buf[slot] = x;
+    const i32 g = wave_append_slot(spill, counter);  // every active lane
+    if (spill) next[g] = x;
+  }
+  __device__ __forceinline__ void add(i32 x0, i32 x1, i32* next, i32* counter) {
+    add1(x0, next, counter);
+    add1(x1, next, counter);
+  }
+  // Every thread of the block, after its last add.
+  __device__ __forceinline__ void flush(i32* next, i32* counter) {
+    __syncthreads();
+    const i32 k = min(n, (i32)APPEND_LDS);
+    if (threadIdx.x == 0 && k > 0) base = atomicAdd(counter, k);
+    __syncthreads();
+    for (i32 t = threadIdx.x; t < k; t += (i32)blockDim.x) next[base + t] = buf[t];
+  }
+};
+
 // Items [base, total) with the given stride, pairs located through LDS P (and
-// the edges' rows from LDS when er is given).
+// the edges' rows from LDS when er is given); appends through ba when given.
 template <int NT>
 __device__ void lds_items(const PeelArgs& a, const Csr& c, const i32* curr, i32 nc, i32 l, i32 r, int variant,
-                          const i64* P, i64 total, i64 base, i64 stride, i32* next, const EdgeRows* er = nullptr) {
+                          const i64* P, i64 total, i64 base, i64 stride, i32* next, const EdgeRows* er = nullptr,
+                          BlockAppend* ba = nullptr) {
   for (i64 b = base; b < total; b += stride) {
     const i64 g = b + threadIdx.x;
     i32 x0 = -1, x1 = -1;
@@ -515,7 +552,10 @@ __device__ void lds_items(const PeelArgs& a, const Csr& c, const i32* curr, i32 
         psl_item(a, c, curr[i], g - P[i], l, r, variant, x0, x1, next, &a.ctl->nnext);
       }
     }
-    append_next(x0, x1, next, &a.ctl->nnext);
+    if (ba)
+      ba->add(x0, x1, next, &a.ctl->nnext);
+    else
+      append_next(x0, x1, next, &a.ctl->nnext);
   }
 }
 
@@ -801,6 +841,7 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_psl_small(PeelArgs a) {
   __shared__ i64 tmp[SMALL_THREADS / PKT_WAVE];
   __shared__ EdgeRows er;
   __shared__ CtlView v;
+  __shared__ BlockAppend ba;
   load_view(ctl, &v);
   if (v.done || v.ncurr == 0 || v.ncurr > SMALL_FRONTIER || !is_fused(v.choice)) return;
   const int nblk = v.choice == TRUSS_CHOICE_FUSED_NARROW ? min((int)gridDim.x, FUSED_NARROW_BLOCKS) : gridDim.x;
@@ -810,10 +851,12 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_psl_small(PeelArgs a) {
   const i32* curr = cur_of(a, sel);
   i32* next = next_of(a, sel);
   if (blockIdx.x == 0 && threadIdx.x == 0) ctl->round_done = 1;
+  if (threadIdx.x == 0) ba.n = 0;  // visible after the prefix's barrier
   mark_prev(a, sel, v.r, v.nprev, (i64)blockIdx.x * SMALL_THREADS + threadIdx.x, (i64)nblk * SMALL_THREADS);
   const i64 total = lds_work_prefix<SMALL_THREADS>(a, c, curr, nc, l, v.variant, P, tmp, &er);
   lds_items<SMALL_THREADS>(a, c, curr, nc, l, r, v.variant, P, total, (i64)blockIdx.x * SMALL_THREADS,
-                           (i64)nblk * SMALL_THREADS, next, &er);
+                           (i64)nblk * SMALL_THREADS, next, &er, &ba);
+  ba.flush(next, &ctl->nnext);
 }
 
 // Work of frontier edge i for the device-wide scan (wide rounds above level 0).
@@ -840,44 +883,6 @@ struct WideLen {
 #ifndef NSAMP
 #define NSAMP 4096
 #endif
-
-// Next-frontier appends of one block, gathered in LDS and written out once at
-// the end of the block's tiles with a single reservation on the global counter
-// (every wave of the grid appending to that one counter would queue its atomics
-// at one address, on each tile's critical path).  Entries past the buffer go
-// straight to the global list.
-#define APPEND_LDS 512
-struct BlockAppend {
-  i32 buf[APPEND_LDS];
-  i32 n, base;
-  __device__ __forceinline__ void add1(i32 x, i32* next, i32* counter) {
-    const u64 mask = __ballot(x >= 0);
-    if (mask == 0) return;
-    const int lane = lane_id(), leader = __ffsll((unsigned long long)mask) - 1;
-    i32 b = 0;
-    if (lane == leader) b = atomicAdd(&n, (i32)__popcll(mask));
-    b = __shfl(b, leader);
-    if (x >= 0) {
-      const i32 slot = b + (i32)__popcll(mask & ((1ull << lane) - 1ull));
-      if (slot < APPEND_LDS)
-        buf[slot] = x;
-      else
-        next[atomicAdd(counter, 1)] = x;
-    }
-  }
-  __device__ __forceinline__ void add(i32 x0, i32 x1, i32* next, i32* counter) {
-    add1(x0, next, counter);
-    add1(x1, next, counter);
-  }
-  // Every thread of the block, after its last add.
-  __device__ __forceinline__ void flush(i32* next, i32* counter) {
-    __syncthreads();
-    const i32 k = min(n, (i32)APPEND_LDS);
-    if (threadIdx.x == 0 && k > 0) base = atomicAdd(counter, k);
-    __syncthreads();
-    for (i32 t = threadIdx.x; t < k; t += PKT_BLOCK) next[base + t] = buf[t];
-  }
-};
 
 struct TileEdge {
   i64 i0;            // frontier index of the staged edge (-1: none)
