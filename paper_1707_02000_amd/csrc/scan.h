@@ -14,7 +14,9 @@
 #include "common.h"
 
 #define SCAN_BLOCKS 1024
+#ifndef SCAN_CHUNK
 #define SCAN_CHUNK 256  // elements per chunk below SCAN_BLOCKS chunks
+#endif
 
 __device__ __forceinline__ int scan_nblocks(i64 count) {
   i64 nb = (count + SCAN_CHUNK - 1) / SCAN_CHUNK;
