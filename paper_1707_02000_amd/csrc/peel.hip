@@ -1095,29 +1095,39 @@ truss_status read_ctl(const Work& w, Ctl* out, hipStream_t s) {
 }
 
 // Device time of every launch of the wide round kernel (event pairs).
+// Timing events stay with the calling thread for its later runs, one pool per
+// device: creating and destroying two events per timed launch costs far more host
+// time than recording them.
+#define CLOCK_DEVICES 16
+thread_local std::vector<hipEvent_t> clock_events[CLOCK_DEVICES];
+
 struct KernelClock {
-  std::vector<hipEvent_t> ev;
+  std::vector<hipEvent_t>* ev = nullptr;
   size_t used = 0;
   hipError_t mark(hipStream_t s) {
-    if (used == ev.size()) {
+    if (!ev) {
+      int d = 0;
+      const hipError_t r = hipGetDevice(&d);
+      if (r != hipSuccess) return r;
+      if (d < 0 || d >= CLOCK_DEVICES) return hipErrorInvalidDevice;
+      ev = &clock_events[d];
+    }
+    if (used == ev->size()) {
       hipEvent_t e;
       // timing only: no system-scope fence (a cache writeback) at every record
-      hipError_t r = hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
+      const hipError_t r = hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
       if (r != hipSuccess) return r;
-      ev.push_back(e);
+      ev->push_back(e);
     }
-    return hipEventRecord(ev[used++], s);
+    return hipEventRecord((*ev)[used++], s);
   }
   float total_ms() {
     float t = 0.f;
     for (size_t i = 0; i + 1 < used; i += 2) {
       float x = 0.f;
-      if (hipEventElapsedTime(&x, ev[i], ev[i + 1]) == hipSuccess) t += x;
+      if (hipEventElapsedTime(&x, (*ev)[i], (*ev)[i + 1]) == hipSuccess) t += x;
     }
     return t;
-  }
-  ~KernelClock() {
-    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
   }
 };
 
