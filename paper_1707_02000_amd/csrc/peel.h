@@ -19,6 +19,9 @@
 #ifndef WIDE_BLOCKS
 #define WIDE_BLOCKS 2048      // blocks of TRUSS_CHOICE_WIDE
 #endif
+#ifndef WIDE_THREADS
+#define WIDE_THREADS PKT_BLOCK  // threads per block of TRUSS_CHOICE_WIDE (one tile of items)
+#endif
 // Single-block continuation (host-driven loop only; see peel_args):
 #ifndef ALONE_FRONTIER
 #define ALONE_FRONTIER 512    // the deciding block goes on alone on frontiers up to this size,

@@ -909,7 +909,7 @@ __device__ void tile_one_edge(const PeelArgs& a, const Csr& c, const i32* curr, 
       te.ns = (i32)((L + step - 1) / step);
     }
     __syncthreads();
-    for (i32 k = threadIdx.x; k < te.ns; k += PKT_BLOCK) samp[k] = c.adj[te.lb + (i64)k * te.step];
+    for (i32 k = threadIdx.x; k < te.ns; k += WIDE_THREADS) samp[k] = c.adj[te.lb + (i64)k * te.step];
     __syncthreads();
   }
   const i64 g = base + threadIdx.x;
@@ -958,7 +958,7 @@ __device__ void tile_one_edge(const PeelArgs& a, const Csr& c, const i32* curr, 
 // the occupancy of the item loop, and no block fences or counts arrivals (a
 // device-scope fence per block costs more than the kernel boundary that orders
 // the round's end).
-__global__ __launch_bounds__(PKT_BLOCK) void k_psl_bsearch(PeelArgs a, const i64* __restrict__ P) {
+__global__ __launch_bounds__(WIDE_THREADS) void k_psl_bsearch(PeelArgs a, const i64* __restrict__ P) {
   Ctl* ctl = a.ctl;
   __shared__ CtlView v;
   __shared__ i64 sp[2];
@@ -976,7 +976,7 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_psl_bsearch(PeelArgs a, const i64
   const i32* curr = cur_of(a, sel);
   i32* next = next_of(a, sel);
   const Csr c = a.csr.pick(v.csel);
-  mark_prev(a, sel, v.r, v.nprev, (i64)blockIdx.x * PKT_BLOCK + threadIdx.x, (i64)nblk * PKT_BLOCK);
+  mark_prev(a, sel, v.r, v.nprev, (i64)blockIdx.x * WIDE_THREADS + threadIdx.x, (i64)nblk * WIDE_THREADS);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ctl->round_done = 1;
     if (total > 0) {  // accounting for the roofline report
@@ -989,14 +989,14 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_psl_bsearch(PeelArgs a, const i64
     te.i0 = -1;
     ba.n = 0;
   }
-  const i64 tiles = (total + PKT_BLOCK - 1) / PKT_BLOCK;
+  const i64 tiles = (total + WIDE_THREADS - 1) / WIDE_THREADS;
   const i64 per = (tiles + nblk - 1) / nblk;
   const i64 t_end = min(tiles, ((i64)blockIdx.x + 1) * per);
   for (i64 tile = (i64)blockIdx.x * per; tile < t_end; ++tile) {
-    const i64 base = tile * PKT_BLOCK;
+    const i64 base = tile * WIDE_THREADS;
     if (threadIdx.x == 0) sp[0] = upper_bound_dev(P, (i64)0, npairs + 1, base) - 1;
     if (threadIdx.x == PKT_WAVE)
-      sp[1] = upper_bound_dev(P, (i64)0, npairs + 1, min(base + PKT_BLOCK, total) - 1) - 1;
+      sp[1] = upper_bound_dev(P, (i64)0, npairs + 1, min(base + WIDE_THREADS, total) - 1) - 1;
     __syncthreads();
     const i64 s0 = sp[0], s1 = sp[1];
     if (s0 == s1 && variant == TRUSS_VARIANT_BSEARCH) {
@@ -1190,7 +1190,7 @@ static truss_status launch_round(const Work& w, const PeelArgs& a, const Ctl& hc
     const int blocks = hc.choice == TRUSS_CHOICE_WIDE_NARROW ? WIDE_NARROW_BLOCKS : WIDE_BLOCKS;
     const bool timed = prof && hc.level > 0;
     if (timed) PKT_HIP(prof->mark(s));
-    hipLaunchKernelGGL(k_psl_bsearch, dim3(blocks), dim3(PKT_BLOCK), 0, s, a, (const i64*)w.X);
+    hipLaunchKernelGGL(k_psl_bsearch, dim3(blocks), dim3(WIDE_THREADS), 0, s, a, (const i64*)w.X);
     if (timed) PKT_HIP(prof->mark(s));
     hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a, (i64)0, 0);
   }
@@ -1212,7 +1212,7 @@ static truss_status enqueue_step(const Work& w, const PeelArgs& a, int G, hipStr
   hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a, (i64)0, 0);
   PKT_HIP(scan_launch(WideLen{a}, w.partial, w.X, &w.ctl->scan_arrive, s));
   if (prof) PKT_HIP(prof->mark(s));
-  hipLaunchKernelGGL(k_psl_bsearch, dim3(WIDE_BLOCKS), dim3(PKT_BLOCK), 0, s, a, (const i64*)w.X);
+  hipLaunchKernelGGL(k_psl_bsearch, dim3(WIDE_BLOCKS), dim3(WIDE_THREADS), 0, s, a, (const i64*)w.X);
   if (prof) PKT_HIP(prof->mark(s));
   PKT_LAUNCH_CHECK();
   return TRUSS_OK;
@@ -1257,7 +1257,7 @@ static truss_status enqueue_seq(const Work& w, const PeelArgs& a, int kind, int 
     PKT_HIP(scan_launch(WideLen{a}, w.partial, w.X, &w.ctl->scan_arrive, s));
     const int blocks = choice == TRUSS_CHOICE_WIDE_NARROW ? WIDE_NARROW_BLOCKS : WIDE_BLOCKS;
     if (prof) PKT_HIP(prof->mark(s));
-    hipLaunchKernelGGL(k_psl_bsearch, dim3(blocks), dim3(PKT_BLOCK), 0, s, a, (const i64*)w.X);
+    hipLaunchKernelGGL(k_psl_bsearch, dim3(blocks), dim3(WIDE_THREADS), 0, s, a, (const i64*)w.X);
     if (prof) PKT_HIP(prof->mark(s));
   }
   hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a, seq, 1);
