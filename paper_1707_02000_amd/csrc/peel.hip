@@ -1133,6 +1133,10 @@ struct KernelClock {
 
 }  // namespace
 
+#ifndef PIPE_ALONE
+#define PIPE_ALONE 0  // 1: the continuation with the pipelined loop too (tuning builds)
+#endif
+
 PeelArgs peel_args(const Work& w, const truss_options& opt) {
   PeelArgs a;
   a.ctl = w.ctl;
@@ -1147,7 +1151,7 @@ PeelArgs peel_args(const Work& w, const truss_options& opt) {
   // The single-block continuation saves host round trips; with launch sequences
   // guessed ahead (pipelined loop) there are none to save and the full grid is
   // faster, so it is off there.
-  const bool cont = opt.device_loop != 3 || opt.trace != nullptr;
+  const bool cont = PIPE_ALONE || opt.device_loop != 3 || opt.trace != nullptr;
   a.alone_frontier = cont ? ALONE_FRONTIER : 0;
   a.alone_items = cont ? ALONE_ITEMS : 0;
   a.alone_alive = cont ? ALONE_ALIVE : 0;
