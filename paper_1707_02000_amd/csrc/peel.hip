@@ -13,17 +13,20 @@
 //                 launch: every block builds the frontier's work prefix in LDS and
 //                 takes a share of the intersection items
 //   k_psl_bsearch wide round over a device-wide scan of the per-edge work (scan.h)
-//   k_decide      one block after each of the above: goes on alone through
-//                 further tiny rounds and short level scans, then picks the launch
-//                 of the round on the frontier left (heuristic, forced, or the MLP
-//                 cost model, which reads features sampled from the frontier)
+//   k_decide      one block after each of the above: ends the round (a counter
+//                 update), with the host-driven loop goes on alone through further
+//                 tiny rounds and short level scans, then picks the launch of the
+//                 round on the frontier left (heuristic, forced, or the MLP cost
+//                 model, which reads features sampled from the frontier) and
+//                 publishes the loop state
 // Edge states are round tags (three in rotation, the previous frontier turned
-// processed by the next round's own blocks), so ending a round is a counter
-// update done by the round's last block to finish.  The round kernels stay lean (their register
-// counts set the occupancy of the item loops); the rest sits in k_decide.
-// The host either reads the control block after every launch sequence, or
-// enqueues steps holding every launch, gated, and checks in batches (optionally
-// as a replayed hipGraph).
+// processed by the next round's own blocks), so ending a round needs no pass over
+// the edges.  The round kernels stay lean (their register counts set the
+// occupancy of the item loops); the rest sits in k_decide.  The host reads the
+// control block after every launch sequence, enqueues steps holding every
+// launch, gated, and checks in batches (optionally as a replayed hipGraph), or
+// (default) keeps launch sequences guessed from the last published state in
+// flight.
 #include <limits.h>
 #include <math.h>
 #include <string.h>
@@ -269,7 +272,7 @@ __device__ void decide(const PeelArgs& a, float* sx, float* sy, float* ha, float
 // Item t of frontier edge e1: chunk t of the shorter row, located in the
 // longer row; for every triangle found with no processed edge, the decrement
 // rule on both other edges (rd: the round index).  Edges that reached l come
-// back in x0, x1 for a wave-aggregated append; more than two from one item are
+// back in x0, x1 for the caller's append; more than two from one item are
 // appended at once.
 __device__ __forceinline__ void psl_item_rows(const PeelArgs& a, const Csr& c, i32 e1, const Rows& r, i64 t, i32 l,
                                               i32 rd, int variant, i32& x0, i32& x1, i32* spill_next,
