@@ -728,7 +728,11 @@ __device__ __forceinline__ void classify(const PeelArgs& a, i32 l, const i32* __
 }
 }  // namespace
 
-__global__ __launch_bounds__(PKT_BLOCK) void k_scan_count(PeelArgs a, i64* __restrict__ part, i32* __restrict__ bmin) {
+// With tbits, the count pass keeps every tile's classification (taken bits in
+// the low half, kept bits in the high half of one word per thread), so that the
+// write pass gathers no support word again.
+__global__ __launch_bounds__(PKT_BLOCK) void k_scan_count(PeelArgs a, i64* __restrict__ part, i32* __restrict__ bmin,
+                                                         u32* __restrict__ tbits) {
   Ctl* ctl = a.ctl;
   if (ctl->done || ctl->ncurr != 0 || ctl->scan_pending) return;
   const int G = gridDim.x;
@@ -742,6 +746,7 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_scan_count(PeelArgs a, i64* __res
     i32 ev[SCAN_ITEMS];
     u32 tk, kp;
     classify(a, l, A, t0, c1, ev, tk, kp, mn);
+    if (tbits) tbits[t0 / SCAN_ITEMS + threadIdx.x] = tk | (kp << 16);
     packed += ((i64)__popc(tk) << 32) | (i64)__popc(kp);
   }
   __shared__ i64 sp[PKT_BLOCK / PKT_WAVE];
@@ -790,7 +795,8 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_scan_count(PeelArgs a, i64* __res
   }
 }
 
-__global__ __launch_bounds__(PKT_BLOCK) void k_scan_write(PeelArgs a, const i64* __restrict__ part) {
+__global__ __launch_bounds__(PKT_BLOCK) void k_scan_write(PeelArgs a, const i64* __restrict__ part,
+                                                         const u32* __restrict__ tbits) {
   Ctl* ctl = a.ctl;
   if (ctl->done || !ctl->scan_pending) return;
   const int G = gridDim.x;
@@ -809,7 +815,18 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_scan_write(PeelArgs a, const i64*
   for (i64 t0 = c0; t0 < c1; t0 += (i64)PKT_BLOCK * SCAN_ITEMS) {
     i32 ev[SCAN_ITEMS];
     u32 tk, kp;
-    classify(a, l, A, t0, c1, ev, tk, kp, mn);
+    if (tbits) {
+#pragma unroll
+      for (int k = 0; k < SCAN_ITEMS; ++k) {
+        const i64 i = t0 + (i64)k * PKT_BLOCK + threadIdx.x;
+        ev[k] = (i < c1) ? A[i] : -1;
+      }
+      const u32 b = tbits[t0 / SCAN_ITEMS + threadIdx.x];
+      tk = b & 0xffffu;
+      kp = b >> 16;
+    } else {
+      classify(a, l, A, t0, c1, ev, tk, kp, mn);
+    }
     i32 pt[SCAN_ITEMS], pk[SCAN_ITEMS], nt, nk;
     stable_tile<PKT_BLOCK>(tk, kp, pt, pk, &nt, &nk, cnt, tmp);
 #pragma unroll
@@ -1166,6 +1183,13 @@ PeelArgs peel_args(const Work& w, const truss_options& opt) {
 }
 
 // Grid of a level scan over nalive entries: one block per tile, at most SCAN_BLOCKS.
+// Scratch for the level scan's tile classification: the working-CSR flag array,
+// when it holds one word per thread of every tile of the longest alive list.
+inline u32* scan_bits(const Work& w) {
+  const i64 tiles = (w.m + (i64)PKT_BLOCK * SCAN_ITEMS - 1) / ((i64)PKT_BLOCK * SCAN_ITEMS);
+  return tiles * PKT_BLOCK * (i64)sizeof(u32) <= w.two_m ? (u32*)w.flag : nullptr;
+}
+
 inline int scan_grid(i64 nalive) {
   const i64 tiles = (nalive + (i64)PKT_BLOCK * SCAN_ITEMS - 1) / ((i64)PKT_BLOCK * SCAN_ITEMS);
   return (int)(tiles < 1 ? 1 : (tiles > SCAN_BLOCKS ? SCAN_BLOCKS : tiles));
@@ -1179,8 +1203,9 @@ static truss_status launch_round(const Work& w, const PeelArgs& a, const Ctl& hc
   if (hc.ncurr == 0) {
     *kind = 0;
     const int G = scan_grid(hc.nalive);
-    hipLaunchKernelGGL(k_scan_count, dim3(G), dim3(PKT_BLOCK), 0, s, a, w.partial, w.bmin);
-    hipLaunchKernelGGL(k_scan_write, dim3(G), dim3(PKT_BLOCK), 0, s, a, (const i64*)w.partial);
+    hipLaunchKernelGGL(k_scan_count, dim3(G), dim3(PKT_BLOCK), 0, s, a, w.partial, w.bmin, scan_bits(w));
+    hipLaunchKernelGGL(k_scan_write, dim3(G), dim3(PKT_BLOCK), 0, s, a, (const i64*)w.partial,
+                       (const u32*)scan_bits(w));
     hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a, (i64)0, 0);
   } else if (hc.choice == CHOICE_NONE) {
     *kind = 0;
@@ -1193,7 +1218,7 @@ static truss_status launch_round(const Work& w, const PeelArgs& a, const Ctl& hc
   } else {
     *kind = 2;
     // level 0: frontier edges lie in no triangle, nothing to intersect or scan
-    if (hc.level > 0) PKT_HIP(scan_launch(WideLen{a}, w.partial, w.X, &w.ctl->scan_arrive, s));
+    if (hc.level > 0) PKT_HIP((scan_launch<WideLen, true>(WideLen{a}, w.partial, w.X, &w.ctl->scan_arrive, s)));
     const int blocks = hc.choice == TRUSS_CHOICE_WIDE_NARROW ? WIDE_NARROW_BLOCKS : WIDE_BLOCKS;
     const bool timed = prof && hc.level > 0;
     if (timed) PKT_HIP(prof->mark(s));
@@ -1212,12 +1237,13 @@ static truss_status launch_round(const Work& w, const PeelArgs& a, const Ctl& hc
 // k_decide ends the previous step's wide round.
 static truss_status enqueue_step(const Work& w, const PeelArgs& a, int G, hipStream_t s, KernelClock* prof) {
   hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a, (i64)0, 0);
-  hipLaunchKernelGGL(k_scan_count, dim3(G), dim3(PKT_BLOCK), 0, s, a, w.partial, w.bmin);
-  hipLaunchKernelGGL(k_scan_write, dim3(G), dim3(PKT_BLOCK), 0, s, a, (const i64*)w.partial);
+  hipLaunchKernelGGL(k_scan_count, dim3(G), dim3(PKT_BLOCK), 0, s, a, w.partial, w.bmin, scan_bits(w));
+  hipLaunchKernelGGL(k_scan_write, dim3(G), dim3(PKT_BLOCK), 0, s, a, (const i64*)w.partial,
+                       (const u32*)scan_bits(w));
   hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a, (i64)0, 0);
   hipLaunchKernelGGL(k_psl_small, dim3(FUSED_BLOCKS), dim3(SMALL_THREADS), 0, s, a);
   hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a, (i64)0, 0);
-  PKT_HIP(scan_launch(WideLen{a}, w.partial, w.X, &w.ctl->scan_arrive, s));
+  PKT_HIP((scan_launch<WideLen, true>(WideLen{a}, w.partial, w.X, &w.ctl->scan_arrive, s)));
   if (prof) PKT_HIP(prof->mark(s));
   hipLaunchKernelGGL(k_psl_bsearch, dim3(WIDE_BLOCKS), dim3(WIDE_THREADS), 0, s, a, (const i64*)w.X);
   if (prof) PKT_HIP(prof->mark(s));
@@ -1255,13 +1281,14 @@ static truss_status enqueue_seq(const Work& w, const PeelArgs& a, int kind, int 
                                 KernelClock* prof, i64 seq) {
   if (kind == SEQ_SCAN) {
     const int G = scan_grid(nalive);
-    hipLaunchKernelGGL(k_scan_count, dim3(G), dim3(PKT_BLOCK), 0, s, a, w.partial, w.bmin);
-    hipLaunchKernelGGL(k_scan_write, dim3(G), dim3(PKT_BLOCK), 0, s, a, (const i64*)w.partial);
+    hipLaunchKernelGGL(k_scan_count, dim3(G), dim3(PKT_BLOCK), 0, s, a, w.partial, w.bmin, scan_bits(w));
+    hipLaunchKernelGGL(k_scan_write, dim3(G), dim3(PKT_BLOCK), 0, s, a, (const i64*)w.partial,
+                       (const u32*)scan_bits(w));
   } else if (kind == SEQ_FUSED) {
     const int blocks = choice == TRUSS_CHOICE_FUSED_NARROW ? FUSED_NARROW_BLOCKS : FUSED_BLOCKS;
     hipLaunchKernelGGL(k_psl_small, dim3(blocks), dim3(SMALL_THREADS), 0, s, a);
   } else if (kind == SEQ_WIDE) {
-    PKT_HIP(scan_launch(WideLen{a}, w.partial, w.X, &w.ctl->scan_arrive, s));
+    PKT_HIP((scan_launch<WideLen, true>(WideLen{a}, w.partial, w.X, &w.ctl->scan_arrive, s)));
     const int blocks = choice == TRUSS_CHOICE_WIDE_NARROW ? WIDE_NARROW_BLOCKS : WIDE_BLOCKS;
     if (prof) PKT_HIP(prof->mark(s));
     hipLaunchKernelGGL(k_psl_bsearch, dim3(blocks), dim3(WIDE_THREADS), 0, s, a, (const i64*)w.X);

@@ -9,7 +9,9 @@
 //   __device__ i64  count()  const;   // number of elements
 //   __device__ i64  len(i64 i) const; // value of element i
 // Output: out[i] = sum of len(0..i-1) for i in [0, count], so out[count] is the
-// total.  `arrive` is a zeroed counter the last block resets.
+// total.  `arrive` is a zeroed counter the last block resets.  With CACHE, pass 1
+// keeps every len(i) in out[i] and pass 2 reads it from there (the same thread
+// reads and then overwrites each entry), for functors whose len is costly.
 #pragma once
 #include "common.h"
 
@@ -24,8 +26,9 @@ __device__ __forceinline__ int scan_nblocks(i64 count) {
   return (int)(nb < (i64)gridDim.x ? nb : (i64)gridDim.x);
 }
 
-template <class F>
-__global__ __launch_bounds__(PKT_BLOCK) void k_scan_reduce(F f, i64* __restrict__ partial, u32* __restrict__ arrive) {
+template <class F, bool CACHE = false>
+__global__ __launch_bounds__(PKT_BLOCK) void k_scan_reduce(F f, i64* __restrict__ partial, u32* __restrict__ arrive,
+                                                          i64* __restrict__ out) {
   if (!f.active()) return;
   const i64 count = f.count();
   const int nb = scan_nblocks(count);
@@ -34,7 +37,11 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_scan_reduce(F f, i64* __restrict_
   const i64 b0 = (i64)blockIdx.x * chunk;
   const i64 b1 = min(count, b0 + chunk);
   i64 s = 0;
-  for (i64 i = b0 + threadIdx.x; i < b1; i += PKT_BLOCK) s += f.len(i);
+  for (i64 i = b0 + threadIdx.x; i < b1; i += PKT_BLOCK) {
+    const i64 v = f.len(i);
+    if (CACHE) out[i] = v;
+    s += v;
+  }
   __shared__ i64 tmp[PKT_BLOCK / PKT_WAVE];
   __shared__ int last;
   s = wave_sum_i64(s);
@@ -65,7 +72,7 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_scan_reduce(F f, i64* __restrict_
   }
 }
 
-template <class F>
+template <class F, bool CACHE = false>
 __global__ __launch_bounds__(PKT_BLOCK) void k_scan_down(F f, const i64* __restrict__ partial,
                                                         i64* __restrict__ out) {
   if (!f.active()) return;
@@ -79,7 +86,7 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_scan_down(F f, const i64* __restr
   i64 running = partial[blockIdx.x];
   for (i64 t = b0; t < b1; t += PKT_BLOCK) {
     const i64 i = t + threadIdx.x;
-    const i64 v = (i < b1) ? f.len(i) : 0;
+    const i64 v = (i < b1) ? (CACHE ? out[i] : f.len(i)) : 0;
     i64 tot;
     const i64 ex = block_excl_scan_i64(v, tmp, &tot);
     if (i < b1) out[i] = running + ex;
@@ -88,10 +95,11 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_scan_down(F f, const i64* __restr
   if ((int)blockIdx.x == nb - 1 && threadIdx.x == 0) out[count] = partial[nb];
 }
 
-template <class F>
+template <class F, bool CACHE = false>
 static inline hipError_t scan_launch(const F& f, i64* partial, i64* out, u32* arrive, hipStream_t stream) {
-  hipLaunchKernelGGL(k_scan_reduce<F>, dim3(SCAN_BLOCKS), dim3(PKT_BLOCK), 0, stream, f, partial, arrive);
-  hipLaunchKernelGGL(k_scan_down<F>, dim3(SCAN_BLOCKS), dim3(PKT_BLOCK), 0, stream, f, partial, out);
+  hipLaunchKernelGGL((k_scan_reduce<F, CACHE>), dim3(SCAN_BLOCKS), dim3(PKT_BLOCK), 0, stream, f, partial, arrive,
+                     out);
+  hipLaunchKernelGGL((k_scan_down<F, CACHE>), dim3(SCAN_BLOCKS), dim3(PKT_BLOCK), 0, stream, f, partial, out);
   return hipGetLastError();
 }
 
