@@ -154,7 +154,12 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_orient(i32 n, i64 two_m, const i6
 #define SUP_BLOCKS 2048        // workgroups of the support kernel (they drain a work queue)
 #endif
 #define SUP_TBL (2 * SUP_DMAX)  // hash slots (power of two)
+#ifndef SUP_CHUNK
 #define SUP_CHUNK 8             // vertices taken from the work queue at a time
+#endif
+#ifndef SUP_UNROLL
+#define SUP_UNROLL 2            // out-row entries per lane in flight
+#endif
 
 // Support by oriented triangle counting (Algorithm 3's scheme, one workgroup per
 // vertex instead of one thread): vertices are ranked by (degree, id) and every
@@ -266,20 +271,26 @@ __global__ __launch_bounds__(SUP_THREADS) void k_support(i32 n, const i64* __res
         const i32 v2 = more2 ? oadj[b + i + 2 * NWV] : 0;
         const i64 vb1 = more1 ? ooff[v1] : 0, ve1 = more1 ? ooff[v1 + 1] : 0;
         i32 c_uv = 0;
-        for (i64 k0 = vb + lane; k0 < ve; k0 += 2 * PKT_WAVE) {  // two entries per lane in flight
-          const i64 k1 = k0 + PKT_WAVE;
-          const i32 w0 = oadj[k0], w1 = k1 < ve ? oadj[k1] : -1;
+        // SUP_UNROLL entries per lane in flight, each with its edge id (coalesced
+        // loads, issued together; the id is not fetched after a hit)
+        for (i64 k0 = vb + lane; k0 < ve; k0 += SUP_UNROLL * PKT_WAVE) {
+          i32 wq[SUP_UNROLL], fq[SUP_UNROLL];
 #pragma unroll
-          for (int q = 0; q < 2; ++q) {
-            const i32 w = q ? w1 : w0;
-            const i64 k = q ? k1 : k0;
+          for (int q = 0; q < SUP_UNROLL; ++q) {
+            const i64 k = k0 + q * PKT_WAVE;
+            wq[q] = k < ve ? oadj[k] : -1;
+            fq[q] = k < ve ? oeid[k] : -1;
+          }
+#pragma unroll
+          for (int q = 0; q < SUP_UNROLL; ++q) {
+            const i32 w = wq[q];
             if (w < 0) continue;
             u32 h = ((u32)w * 0x9E3779B1u) >> (32 - tbits);
             for (;;) {
               const i32 key = keys[h];
               if (key == w) {
                 atomicAdd(&cnt[slot[h]], 1);  // edge (u, w)
-                atomicAdd(&sw[oeid[k]], SW_ONE);  // edge (v, w)
+                atomicAdd(&sw[fq[q]], SW_ONE);  // edge (v, w)
                 ++c_uv;
                 break;
               }
