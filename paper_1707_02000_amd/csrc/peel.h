@@ -5,7 +5,9 @@
 
 #define SCAN_ITEMS 16        // alive-list entries per thread per tile of a level scan
 #define SMALL_FRONTIER 2048  // frontiers up to this size may run as one fused launch
+#ifndef SMALL_THREADS
 #define SMALL_THREADS 512    // threads per block of the fused launch
+#endif
 #define FUSED_NARROW_BLOCKS 32
 #define WIDE_NARROW_BLOCKS 256
 // Launch constants a build may override (tuning runs):
