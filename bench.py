@@ -160,8 +160,8 @@ def main():
         print(json.dumps({"copy_bytes": src.numel() * 4, "copies": 5}))
         return
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); "
-              "multi-GPU sharding is described in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py: the library runs one decomposition on one GPU (got --gpus {args.gpus}); "
+              "sharding across GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
