@@ -117,9 +117,10 @@ typedef struct {
   int32_t device_loop;       /* 0 = host-driven: the host reads the loop state after every launch
                                 sequence; 1 = device-driven: batches of gated steps between host
                                 checks; 2 = as 1, the steps replayed from a captured hipGraph;
-                                3 = pipelined host loop: a guessed next sequence is always in
-                                flight, the loop state is published to host-mapped memory and
-                                polled (default 3; a trace forces 0, profile turns 2 into 1) */
+                                3 = pipelined host loop: launch sequences guessed from the last
+                                published loop state stay in flight (two by default), the loop
+                                state is published to host-mapped memory and polled (default 3;
+                                a trace forces 0, profile turns 2 into 1) */
   int32_t validate;          /* 1 = check the input CSR before any other work (default 1) */
   int32_t owner_rule;        /* 0 = the lower edge id owns a two-frontier-edge triangle (the
                                 paper's rule, default); 1 = the higher id (the paper's stated
