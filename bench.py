@@ -60,8 +60,9 @@ def measured_traffic(workload):
     return float(fields["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(sample_name="rmat16"):
-    """The CPU oracle (serial bucket peel, one thread) on a bounded sample of the same recipe."""
+def cpu_baseline(sample_name="rmat17"):
+    """The CPU oracle (serial bucket peel, one thread) on a bounded sample of the same recipe
+    (R-MAT scale 17: about 20 s of one core)."""
     import graphgen as gg
     import oracle
 
@@ -70,7 +71,7 @@ def cpu_baseline(sample_name="rmat16"):
     oracle.truss(g)
     dt = time.perf_counter() - t0
     return {"value": g.m / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
-            "sample": f"{sample_name}: R-MAT scale 16, edge factor 16, same (a,b,c,d) recipe, seed 1 "
+            "sample": f"{sample_name}: R-MAT scale {sample_name[4:]}, edge factor 16, same (a,b,c,d) recipe, seed 1 "
                       f"(m={g.m}); one full serial decomposition, {dt:.1f} s"}
 
 
