@@ -87,12 +87,19 @@ def _timed(fn, steps, warmup, torch):
 
 
 def extras(pkt, torch, gg, off20, adj20, m20, ms20, steps):
-    """The other parts of the metric: learned dispatch vs the plain heuristic (R-MAT s20
-    and s24), R-MAT s24 itself, and batched (one union level loop) vs one graph after
-    another.  Each timed like the main line (inputs resident, one warm-up)."""
+    """The other parts of the metric: the level loop's drivers, learned dispatch vs the
+    plain heuristic (R-MAT s20 and s24), R-MAT s24 itself, and batched (one union level
+    loop) vs one graph after another.  Inputs resident, as for the main line."""
     from paper_1707_02000_amd import tuner
 
     out = {}
+    # the level loop's drivers on the same graph (pipelined is the main line's)
+    drivers = {}
+    for mode in ("host", "device", "graph", "pipelined"):
+        t = _timed(lambda: pkt.truss_decompose(off20, adj20, validate=False, device_loop=mode), 2, 1, torch)
+        drivers[mode] = round(t * 1e3, 2)
+    out["loop_drivers_rmat20_ms"] = drivers
+    print(f"bench: loop drivers rmat20 {drivers}", file=sys.stderr, flush=True)
     W = tuner.load_weights()
     t = _timed(lambda: pkt.truss_decompose(off20, adj20, validate=False, variant="learned", mlp_weights=W),
                steps, 1, torch)
