@@ -15,6 +15,9 @@ Contents
     any size, given a peeling order: every edge of trussness k lies in >= k-2
     triangles of the edges of trussness >= k, and no edge had more than k-2 triangles
     left when the order removed it; run on sampled edges at full scale.
+  * ``ktruss`` -- the maximal k-trusses given the trussness (Background section): the
+    connected components of the edges of trussness >= k, each named by its smallest
+    edge id.
   * ``psl_model`` -- a step-by-step model of the level-synchronous peeling
     (Algorithms 4 and 5 of the PKT section) whose threads interleave at random, to
     check the concurrency rules (lower-edge-id ownership, clamp and restore).
