@@ -215,6 +215,30 @@ truss_status truss_edge_list(int32_t n, const int64_t* offsets, const int32_t* a
                              int32_t* el_v, void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * The maximal k-trusses, given the trussness (Background section: a k-truss is
+ * a maximal connected subgraph in which every edge lies in at least k - 2
+ * triangles of the subgraph).  The edges of trussness >= k contain every k-truss
+ * and have that property themselves, so the k-trusses are their connected
+ * components (two such edges that share a vertex belong to the same k-truss).
+ *   n, m             vertices and edges of the graph (n >= 0, 0 <= m < 2^31)
+ *   el_u, el_v       device, int32[m]: edge endpoints, e.g. from truss_edge_list
+ *   trussness        device, int32[m], e.g. from truss_decompose
+ *   k                >= 2
+ *   label            device, int32[m] out: for an edge of trussness >= k, the
+ *                    smallest edge id of its k-truss (so the labels are unique and
+ *                    equal labels mean the same k-truss); -1 for the other edges
+ *   num_trusses      host, may be NULL: the number of k-trusses
+ * The caller owns every buffer.  Workspace: truss_ktruss_workspace_bytes(n)
+ * bytes at 256-byte alignment.  Errors: TRUSS_E_ARG (bad n, m or k, or a NULL
+ * pointer with m > 0), TRUSS_E_RANGE (an endpoint of an edge of trussness >= k
+ * outside [0, n); label is then undefined), TRUSS_E_WORKSPACE, TRUSS_E_DEVICE.
+ */
+truss_status truss_ktruss_workspace_bytes(int32_t n, size_t* bytes);
+truss_status truss_ktruss(int32_t n, int64_t m, const int32_t* el_u, const int32_t* el_v,
+                          const int32_t* trussness, int32_t k, int32_t* label, int32_t* num_trusses,
+                          void* workspace, size_t workspace_bytes, void* stream);
+
+/*
  * Batched decomposition of many independent graphs.  By default they are
  * decomposed together as one disjoint union (one level loop and one launch
  * sequence for the whole batch; trussness is per connected component and the

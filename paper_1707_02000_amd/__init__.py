@@ -132,6 +132,9 @@ _SIGS = {
                       + [ctypes.c_void_p] * 2),
     "truss_edge_list": (ctypes.c_int, [ctypes.c_int32] + [ctypes.c_void_p] * 5 + [ctypes.c_size_t]
                         + [ctypes.c_void_p]),
+    "truss_ktruss_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p]),
+    "truss_ktruss": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64] + [ctypes.c_void_p] * 3 + [ctypes.c_int32]
+                     + [ctypes.c_void_p] * 3 + [ctypes.c_size_t, ctypes.c_void_p]),
     "truss_batched_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
                                                      ctypes.c_void_p, ctypes.c_void_p]),
     "truss_decompose_batched": (ctypes.c_int, [ctypes.c_int32] + [ctypes.c_void_p] * 5
@@ -345,6 +348,32 @@ def edge_list(offsets, adj, *, stream=None):
     _check(lib.truss_edge_list(n, _ptr(off_t), _ptr(adj_t), _ptr(eu), _ptr(ev), ctypes.c_void_p(wptr), nb,
                                _stream(torch, stream)))
     return torch.stack([eu[:m], ev[:m]], dim=1)
+
+
+def ktruss(n, edges, trussness, k, *, stream=None, out=None):
+    """The maximal k-trusses: per edge the smallest edge id of its k-truss (-1 below k).
+
+    edges: (m, 2) int32 endpoints (as from edge_list) or a pair of int32 [m] arrays;
+    trussness: int32 [m].  Returns (labels int32 [m] CUDA tensor, number of k-trusses).
+    """
+    torch = _torch()
+    lib = load()
+    if isinstance(edges, (tuple, list)):
+        eu, ev = (_dev(x, torch.int32, torch).contiguous() for x in edges)
+    else:
+        e = _dev(edges, torch.int32, torch).reshape(-1, 2)
+        eu, ev = e[:, 0].contiguous(), e[:, 1].contiguous()
+    tau = _dev(trussness, torch.int32, torch).contiguous()
+    m = tau.numel()
+    nb = ctypes.c_size_t(0)
+    _check(lib.truss_ktruss_workspace_bytes(int(n), ctypes.byref(nb)))
+    _buf, wptr = alloc_workspace(nb.value)
+    if out is None:
+        out = torch.empty(max(m, 1), dtype=torch.int32, device="cuda")
+    count = ctypes.c_int32(0)
+    _check(lib.truss_ktruss(int(n), m, _ptr(eu), _ptr(ev), _ptr(tau), int(k), _ptr(out), ctypes.byref(count),
+                            ctypes.c_void_p(wptr), nb.value, _stream(torch, stream)))
+    return out[:m], int(count.value)
 
 
 def truss_decompose_batched(vtx_off, adj_off, offsets_packed, adj_packed, *, variant="auto", validate=True,
