@@ -87,7 +87,7 @@ def _timed(fn, steps, warmup, torch):
 
 
 def extras(pkt, torch, gg, off20, adj20, m20, ms20, steps):
-    """The other parts of the metric: the level loop's drivers, learned dispatch vs the
+    """The other parts of the metric: the level loop's drivers, the k-truss listing, learned dispatch vs the
     plain heuristic (R-MAT s20 and s24), R-MAT s24 itself, and batched (one union level
     loop) vs one graph after another.  Inputs resident, as for the main line."""
     from paper_1707_02000_amd import tuner
@@ -100,6 +100,22 @@ def extras(pkt, torch, gg, off20, adj20, m20, ms20, steps):
         drivers[mode] = round(t * 1e3, 2)
     out["loop_drivers_rmat20_ms"] = drivers
     print(f"bench: loop drivers rmat20 {drivers}", file=sys.stderr, flush=True)
+    # the maximal k-trusses from the trussness (three passes over the edges, two over
+    # the vertices: 32 B per edge and 16 B per vertex algorithmic)
+    tau20 = pkt.truss_decompose(off20, adj20, validate=False)
+    el20 = pkt.edge_list(off20, adj20)
+    n20 = int(off20.numel()) - 1
+    tmax = int(tau20.max().item())
+    kt = {}
+    for k in (3, tmax // 2, tmax):
+        t = _timed(lambda: pkt.ktruss(n20, el20, tau20, k), 3, 1, torch)
+        _, cnt = pkt.ktruss(n20, el20, tau20, k)
+        gbs = (32 * m20 + 16 * n20) / t / 1e9
+        kt[str(k)] = {"ms": round(t * 1e3, 3), "trusses": cnt, "edges_per_s": m20 / t, "GB/s": gbs,
+                      "frac_of_hbm": gbs / HBM_PEAK_GBS}
+    out["ktruss_rmat20"] = kt
+    print(f"bench: k-truss listing rmat20 { {k: v['ms'] for k, v in kt.items()} } ms", file=sys.stderr, flush=True)
+    del tau20, el20
     W = tuner.load_weights()
     t = _timed(lambda: pkt.truss_decompose(off20, adj20, validate=False, variant="learned", mlp_weights=W),
                steps, 1, torch)

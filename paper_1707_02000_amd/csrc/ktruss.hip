@@ -9,7 +9,7 @@
 // smaller one with a compare-and-swap (parents only ever decrease, so there are
 // no cycles and every find ends), finds halve their paths as they go; then one
 // pass points every vertex at its root, a second takes the smallest edge id of
-// every root's edges, and a third labels the edges with it.
+// every set (its root's first edge), and a third labels the edges with it.
 #include <limits.h>
 
 #include "common.h"
@@ -81,13 +81,35 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_kt_compress(i32 n, i32* par) {
     par[v] = uf_find(par, (i32)v);
 }
 
+// Smallest edge id of every set.  A root is the smallest vertex of its set
+// (parents only decrease), so every edge of the set leaves from the root or from
+// a larger vertex, and in row-major edge order the smallest id is the root's
+// first edge: only edges whose lower endpoint is a root take part, and the lanes
+// of a wave that share one (consecutive edges of one row) take their minimum
+// first, so one atomic per wave and row reaches memory.
 __global__ __launch_bounds__(PKT_BLOCK) void k_kt_first(i64 m, const i32* __restrict__ eu,
                                                        const i32* __restrict__ tau, i32 k,
                                                        const i32* __restrict__ par, i32* __restrict__ first,
                                                        const u32* __restrict__ err) {
   if (*err) return;
-  for (i64 e = (i64)blockIdx.x * PKT_BLOCK + threadIdx.x; e < m; e += (i64)gridDim.x * PKT_BLOCK)
-    if (tau[e] >= k) atomicMin(&first[par[eu[e]]], (i32)e);
+  const i64 stride = (i64)gridDim.x * PKT_BLOCK;
+  const i64 m_up = (m + PKT_WAVE - 1) / PKT_WAVE * PKT_WAVE;  // whole waves stay in the loop
+  for (i64 e = (i64)blockIdx.x * PKT_BLOCK + threadIdx.x; e < m_up; e += stride) {
+    i32 r = -1;
+    if (e < m && tau[e] >= k) {
+      const i32 u = eu[e];
+      if (par[u] == u) r = u;
+    }
+    u64 todo = __ballot(r >= 0);
+    while (todo) {  // one round per distinct root among the lanes
+      const int lead = __ffsll((unsigned long long)todo) - 1;
+      const i32 rl = __shfl(r, lead);
+      const u64 same = __ballot(r == rl);
+      const i32 mn = wave_min_i32(r == rl ? (i32)e : INT_MAX);
+      if (lane_id() == lead) atomicMin(&first[rl], mn);
+      todo &= ~same;
+    }
+  }
 }
 
 __global__ __launch_bounds__(PKT_BLOCK) void k_kt_label(i64 m, const i32* __restrict__ eu,
