@@ -15,6 +15,8 @@ Contents
     any size, given a peeling order: every edge of trussness k lies in >= k-2
     triangles of the edges of trussness >= k, and no edge had more than k-2 triangles
     left when the order removed it; run on sampled edges at full scale.
+  * ``kcore`` -- core numbers of the vertices (Batagelj-Zaversnik bucket order, in C),
+    pinned against the k-core definition in ``definition``.
   * ``ktruss`` -- the maximal k-trusses given the trussness (Background section): the
     connected components of the edges of trussness >= k, each named by its smallest
     edge id.
@@ -64,6 +66,8 @@ def _load():
     lib.oracle_support.restype = ctypes.c_int64
     lib.oracle_truss.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp]
     lib.oracle_truss.restype = ctypes.c_int64
+    lib.oracle_kcore.argtypes = [ctypes.c_int32, vp, vp, vp]
+    lib.oracle_kcore.restype = ctypes.c_int64
     _lib = lib
     return lib
 
@@ -143,3 +147,14 @@ def edge_ids(g):
     if r < 0:
         raise OracleInputError(f"oracle_edge_ids failed ({r})")
     return np.stack([eu[:m], ev[:m]], axis=1), eid[:two_m]
+
+
+def kcore(g) -> np.ndarray:
+    """Core number of every vertex (int32), by the bucket order in C."""
+    n, off, adj = _csr(g)
+    core = np.zeros(max(n, 1), np.int32)
+    r = _load().oracle_kcore(n, _ptr(off), _ptr(adj), _ptr(core))
+    if r < 0:
+        raise OracleInputError(f"oracle_kcore failed ({r})")
+    return core[:n]
+

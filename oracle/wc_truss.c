@@ -238,3 +238,69 @@ out:
   free(bin);
   return result;
 }
+
+/* Core numbers (k-core decomposition) by Batagelj and Zaversnik's bucket order:
+ * vertices sorted by degree in bins; the vertex of least current degree is
+ * removed, its core number is that degree, and every neighbour of larger degree
+ * moves to the front of its bin and loses one.  Returns the largest core number,
+ * or -1 on allocation failure. */
+int64_t oracle_kcore(int32_t n, const int64_t* off, const int32_t* adj, int32_t* core) {
+  if (n <= 0) return 0;
+  int32_t md = 0;
+  int32_t* deg = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t* pos = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t* vert = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  if (!deg || !pos || !vert) {
+    free(deg); free(pos); free(vert);
+    return -1;
+  }
+  for (int32_t v = 0; v < n; ++v) {
+    deg[v] = (int32_t)(off[v + 1] - off[v]);
+    if (deg[v] > md) md = deg[v];
+  }
+  int64_t* bin = (int64_t*)calloc((size_t)md + 2, sizeof(int64_t));
+  if (!bin) {
+    free(deg); free(pos); free(vert);
+    return -1;
+  }
+  for (int32_t v = 0; v < n; ++v) bin[deg[v]] += 1;
+  int64_t start = 0;
+  for (int32_t d = 0; d <= md; ++d) {  /* bin[d] -> first position of degree d */
+    const int64_t c = bin[d];
+    bin[d] = start;
+    start += c;
+  }
+  for (int32_t v = 0; v < n; ++v) {
+    pos[v] = (int32_t)bin[deg[v]];
+    vert[pos[v]] = v;
+    bin[deg[v]] += 1;
+  }
+  for (int32_t d = md; d >= 1; --d) bin[d] = bin[d - 1];
+  bin[0] = 0;
+  int64_t kmax = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    const int32_t v = vert[i];
+    core[v] = deg[v];
+    if (deg[v] > kmax) kmax = deg[v];
+    for (int64_t j = off[v]; j < off[v + 1]; ++j) {
+      const int32_t u = adj[j];
+      if (deg[u] > deg[v]) {  /* u not yet removed: swap it to the front of its bin */
+        const int32_t du = deg[u];
+        const int32_t pu = pos[u];
+        const int32_t pw = (int32_t)bin[du];
+        const int32_t w = vert[pw];
+        if (u != w) {
+          pos[u] = pw;
+          vert[pu] = w;
+          pos[w] = pu;
+          vert[pw] = u;
+        }
+        bin[du] += 1;
+        deg[u] -= 1;
+      }
+    }
+  }
+  free(deg); free(pos); free(vert); free(bin);
+  return kmax;
+}
+

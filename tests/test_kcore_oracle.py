@@ -1,4 +1,5 @@
-"""Pins for the oracle's core numbers (oracle/definition.py, kcore_numbers): the
+"""Pins for the oracle's core numbers (oracle/definition.py, kcore_numbers, and the
+C bucket order behind oracle.kcore): the
 k-core definition by brute force (repeated deletion of vertices of degree < k; the
 core number of v is the largest k whose k-core holds v) on every graph with 5
 vertices and on random graphs, and closed forms (isolated vertices, paths, stars,
@@ -67,3 +68,29 @@ def test_closed_forms():
     # K5 and a triangle joined by a pendant path: 4, 2 and 1
     edges = list(itertools.combinations(range(5), 2)) + [(5, 6), (6, 7), (5, 7), (4, 8), (8, 5)]
     assert D.kcore_numbers(9, edges).tolist() == [4, 4, 4, 4, 4, 2, 2, 2, 2]
+
+
+@pytest.mark.parametrize("seed", range(25))
+def test_bucket_order_in_c_matches_the_definition(seed):
+    import graphgen as gg
+    import oracle
+
+    rng = random.Random(1000 + seed)
+    n = rng.randint(1, 80)
+    p = rng.uniform(0.0, 0.3)
+    edges = [(u, v) for u in range(n) for v in range(u + 1, n) if rng.random() < p]
+    for _ in range(rng.randint(0, 2)):  # planted cliques give deeper cores
+        vs = sorted(rng.sample(range(n), min(n, rng.randint(3, 10))))
+        edges += list(itertools.combinations(vs, 2))
+    edges = sorted(set(edges))
+    g = gg.from_edges(n, edges)
+    assert np.array_equal(oracle.kcore(g), cores_by_definition(n, edges))
+
+
+def test_bucket_order_on_a_medium_graph():
+    import graphgen as gg
+    import oracle
+
+    g = gg.workload("rmat12", seed=4)
+    edges = [tuple(map(int, p)) for p in oracle.edge_list(g)]
+    assert np.array_equal(oracle.kcore(g), D.kcore_numbers(g.n, edges))
