@@ -87,9 +87,10 @@ def _timed(fn, steps, warmup, torch):
 
 
 def extras(pkt, torch, gg, off20, adj20, m20, ms20, steps):
-    """The other parts of the metric: the level loop's drivers, the k-truss listing, learned dispatch vs the
-    plain heuristic (R-MAT s20 and s24), R-MAT s24 itself, and batched (one union level
-    loop) vs one graph after another.  Inputs resident, as for the main line."""
+    """The other parts of the metric: the level loop's drivers, the k-truss listing, core
+    numbers, learned dispatch vs the plain heuristic (R-MAT s20 and s24), R-MAT s24 itself,
+    and batched (one union level loop) vs one graph after another.  Inputs resident, as
+    for the main line."""
     from paper_1707_02000_amd import tuner
 
     out = {}
@@ -116,6 +117,11 @@ def extras(pkt, torch, gg, off20, adj20, m20, ms20, steps):
     out["ktruss_rmat20"] = kt
     print(f"bench: k-truss listing rmat20 { {k: v['ms'] for k, v in kt.items()} } ms", file=sys.stderr, flush=True)
     del tau20, el20
+    # core numbers (level-synchronous vertex peeling; the host reads counters each round)
+    tk = _timed(lambda: pkt.kcore(off20, adj20), 3, 1, torch)
+    _, cmax = pkt.kcore(off20, adj20)
+    out["kcore_rmat20"] = {"ms": round(tk * 1e3, 3), "max_core": cmax, "edges_per_s": m20 / tk}
+    print(f"bench: k-core rmat20 {tk * 1e3:.2f} ms, max core {cmax}", file=sys.stderr, flush=True)
     W = tuner.load_weights()
     t = _timed(lambda: pkt.truss_decompose(off20, adj20, validate=False, variant="learned", mlp_weights=W),
                steps, 1, torch)

@@ -239,6 +239,25 @@ truss_status truss_ktruss(int32_t n, int64_t m, const int32_t* el_u, const int32
                           void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * Core numbers of every vertex (k-core decomposition: the k-core is the maximal
+ * subgraph of minimum degree >= k, and the core number of v the largest k whose
+ * k-core holds v), by the level-synchronous vertex peeling that the PKT section
+ * carries over to edges (related-work section, parallel k-core decomposition).
+ *   n, offsets, adj  the CSR contract of truss_decompose (device); isolated
+ *                    vertices get core number 0
+ *   core             device, int32[n] out
+ *   max_core         host, may be NULL: the largest core number
+ * The caller owns every buffer.  Workspace: truss_kcore_workspace_bytes(n)
+ * bytes at 256-byte alignment.  The host reads a few counters per round (one
+ * stream synchronisation each).  Errors: TRUSS_E_ARG, TRUSS_E_RANGE (offsets out
+ * of order or past offsets[n], or a neighbour id outside [0, n); core is then
+ * undefined), TRUSS_E_WORKSPACE, TRUSS_E_DEVICE, TRUSS_E_INTERNAL.
+ */
+truss_status truss_kcore_workspace_bytes(int32_t n, size_t* bytes);
+truss_status truss_kcore(int32_t n, const int64_t* offsets, const int32_t* adj, int32_t* core, int32_t* max_core,
+                         void* workspace, size_t workspace_bytes, void* stream);
+
+/*
  * Batched decomposition of many independent graphs.  By default they are
  * decomposed together as one disjoint union (one level loop and one launch
  * sequence for the whole batch; trussness is per connected component and the

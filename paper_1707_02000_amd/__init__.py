@@ -133,6 +133,8 @@ _SIGS = {
     "truss_edge_list": (ctypes.c_int, [ctypes.c_int32] + [ctypes.c_void_p] * 5 + [ctypes.c_size_t]
                         + [ctypes.c_void_p]),
     "truss_ktruss_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p]),
+    "truss_kcore_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p]),
+    "truss_kcore": (ctypes.c_int, [ctypes.c_int32] + [ctypes.c_void_p] * 5 + [ctypes.c_size_t, ctypes.c_void_p]),
     "truss_ktruss": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64] + [ctypes.c_void_p] * 3 + [ctypes.c_int32]
                      + [ctypes.c_void_p] * 3 + [ctypes.c_size_t, ctypes.c_void_p]),
     "truss_batched_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
@@ -374,6 +376,23 @@ def ktruss(n, edges, trussness, k, *, stream=None, out=None):
     _check(lib.truss_ktruss(int(n), m, _ptr(eu), _ptr(ev), _ptr(tau), int(k), _ptr(out), ctypes.byref(count),
                             ctypes.c_void_p(wptr), nb.value, _stream(torch, stream)))
     return out[:m], int(count.value)
+
+
+def kcore(offsets, adj, *, stream=None):
+    """Core numbers of every vertex (int32 [n] CUDA tensor) and the largest one."""
+    torch = _torch()
+    lib = load()
+    off_t = _dev(offsets, torch.int64, torch)
+    adj_t = _dev(adj, torch.int32, torch)
+    n = off_t.numel() - 1
+    nb = ctypes.c_size_t(0)
+    _check(lib.truss_kcore_workspace_bytes(int(n), ctypes.byref(nb)))
+    _buf, wptr = alloc_workspace(nb.value)
+    out = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+    cmax = ctypes.c_int32(0)
+    _check(lib.truss_kcore(int(n), _ptr(off_t), _ptr(adj_t), _ptr(out), ctypes.byref(cmax), ctypes.c_void_p(wptr),
+                           nb.value, _stream(torch, stream)))
+    return out[:n], int(cmax.value)
 
 
 def truss_decompose_batched(vtx_off, adj_off, offsets_packed, adj_packed, *, variant="auto", validate=True,
