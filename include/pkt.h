@@ -248,8 +248,8 @@ truss_status truss_ktruss(int32_t n, int64_t m, const int32_t* el_u, const int32
  *   core             device, int32[n] out
  *   max_core         host, may be NULL: the largest core number
  * The caller owns every buffer.  Workspace: truss_kcore_workspace_bytes(n)
- * bytes at 256-byte alignment.  The host reads a few counters per round (one
- * stream synchronisation each).  Errors: TRUSS_E_ARG, TRUSS_E_RANGE (offsets out
+ * bytes at 256-byte alignment.  The host copies the counters back once per
+ * round and once per level (one stream synchronisation each).  Errors: TRUSS_E_ARG, TRUSS_E_RANGE (offsets out
  * of order or past offsets[n], or a neighbour id outside [0, n); core is then
  * undefined), TRUSS_E_WORKSPACE, TRUSS_E_DEVICE, TRUSS_E_INTERNAL.
  */

@@ -11,7 +11,8 @@
 // already sits at k), so a degree never drops below the level.  The level ends
 // when a round finds no new vertex.  Frontier items are the adjacency slots of
 // the frontier vertices, one lane each, located through a device-wide prefix of
-// the row lengths (scan.h).  The host reads three counters per round.
+// the row lengths (scan.h).  The host reads the counters once per round and once
+// per level scan.
 #include <limits.h>
 
 #include "common.h"
@@ -25,7 +26,8 @@ inline int kc_grid(i64 count) {
 }
 
 struct KcCounters {
-  i32 nfound, nkeep, minabove, nnext;
+  i32 nfound, nkeep, minabove;
+  i32 nnext[2];  // next-frontier sizes of alternate rounds
   u32 arrive, err;
 };
 
@@ -44,28 +46,64 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_kc_init(i32 n, i64 two_m, const i
 }
 
 // Alive vertices of degree k -> frontier; of larger degree -> the next alive list.
+// A block takes KC_TILE entries (KC_PER per thread, coalesced) and reserves its
+// places in both lists with one atomic each: per-wave reservations on two
+// counters that every wave of a million-vertex scan hits serialised the scan.
+constexpr int KC_PER = 8;
+constexpr int KC_TILE = KC_PER * PKT_BLOCK;
+
 __global__ __launch_bounds__(PKT_BLOCK) void k_kc_scan(i32 na, const i32* __restrict__ A, i32 k,
                                                       const i32* __restrict__ deg, i32* __restrict__ F,
                                                       i32* __restrict__ Aout, KcCounters* cnt) {
+  __shared__ i64 tmp[PKT_BLOCK / PKT_WAVE];
+  __shared__ i32 base[2];
   i32 mn = INT_MAX;
-  const i64 na_up = ((i64)na + PKT_WAVE - 1) / PKT_WAVE * PKT_WAVE;  // whole waves stay in the loop
-  for (i64 i = (i64)blockIdx.x * PKT_BLOCK + threadIdx.x; i < na_up; i += (i64)gridDim.x * PKT_BLOCK) {
-    const i32 v = i < na ? A[i] : -1;
-    const i32 d = v >= 0 ? deg[v] : -1;
-    const bool take = v >= 0 && d == k, keep = v >= 0 && d > k;
-    if (keep) mn = min(mn, d);
-    const i32 st = wave_append_slot(take, &cnt->nfound);
-    if (take) F[st] = v;
-    const i32 sk = wave_append_slot(keep, &cnt->nkeep);
-    if (keep) Aout[sk] = v;
+  const i64 tiles = ((i64)na + KC_TILE - 1) / KC_TILE;
+  for (i64 t = blockIdx.x; t < tiles; t += gridDim.x) {  // uniform over the block
+    i32 v[KC_PER];
+    u32 take = 0, keep = 0;
+    i32 ct = 0, ck = 0;
+#pragma unroll
+    for (int j = 0; j < KC_PER; ++j) {
+      const i64 i = t * KC_TILE + j * PKT_BLOCK + threadIdx.x;
+      v[j] = i < na ? A[i] : -1;
+      const i32 d = v[j] >= 0 ? deg[v[j]] : -1;
+      if (d == k) {
+        take |= 1u << j;
+        ++ct;
+      } else if (d > k) {
+        keep |= 1u << j;
+        ++ck;
+        mn = min(mn, d);
+      }
+    }
+    i64 tot;
+    const i64 pre = block_excl_scan_i64(((i64)ct << 32) | (i64)ck, tmp, &tot);
+    if (threadIdx.x == 0) {
+      const i32 tt = (i32)(tot >> 32), tk = (i32)(tot & 0xffffffff);
+      base[0] = tt ? atomicAdd(&cnt->nfound, tt) : 0;
+      base[1] = tk ? atomicAdd(&cnt->nkeep, tk) : 0;
+    }
+    __syncthreads();
+    i32 pt = base[0] + (i32)(pre >> 32), pk = base[1] + (i32)(pre & 0xffffffff);
+#pragma unroll
+    for (int j = 0; j < KC_PER; ++j) {
+      if (take >> j & 1u) F[pt++] = v[j];
+      if (keep >> j & 1u) Aout[pk++] = v[j];
+    }
+    __syncthreads();  // base[] is rewritten by the next tile
   }
   mn = wave_min_i32(mn);
   if (lane_id() == 0 && mn != INT_MAX) atomicMin(&cnt->minabove, mn);
 }
 
-__global__ __launch_bounds__(PKT_BLOCK) void k_kc_mark(i32 nf, const i32* __restrict__ F, i32 k,
-                                                      i32* __restrict__ core) {
-  for (i64 i = (i64)blockIdx.x * PKT_BLOCK + threadIdx.x; i < nf; i += (i64)gridDim.x * PKT_BLOCK) core[F[i]] = k;
+// Level counters back to their start (the error flag stays).
+__global__ void k_kc_reset(KcCounters* cnt) {
+  cnt->nfound = 0;
+  cnt->nkeep = 0;
+  cnt->minabove = INT_MAX;
+  cnt->nnext[0] = 0;
+  cnt->nnext[1] = 0;
 }
 
 // Row length of frontier vertex i, for the prefix over the round's items.
@@ -81,16 +119,23 @@ struct FrontierRows {
   }
 };
 
-// One lane per adjacency slot of the frontier: the neighbour loses one unit if it
-// is alive and above the level; reaching k + 1 -> k puts it in the next frontier.
+// One lane per adjacency slot of the frontier: the neighbour loses one unit if its
+// degree is above the level; reaching k + 1 -> k puts it in the next frontier.
+// Vertices of this or an earlier level sit at or below k and are never touched,
+// so the degree test alone keeps them out.  The first nf lanes also mark the
+// frontier with k.  The round appends to nnext[sel] and clears nnext[sel ^ 1] for
+// the round after it (the host has read that one already).
 __global__ __launch_bounds__(PKT_BLOCK) void k_kc_round(i32 n, i32 nf, const i32* __restrict__ F,
                                                        const i64* __restrict__ P, const i64* __restrict__ off,
-                                                       const i32* __restrict__ adj, i32 k,
-                                                       const i32* __restrict__ core, i32* __restrict__ deg,
-                                                       i32* __restrict__ next, KcCounters* cnt) {
+                                                       const i32* __restrict__ adj, i32 k, i32* __restrict__ core,
+                                                       i32* __restrict__ deg, i32* __restrict__ next, int sel,
+                                                       KcCounters* cnt) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) cnt->nnext[sel ^ 1] = 0;
   const i64 total = P[nf];
-  const i64 total_up = (total + PKT_WAVE - 1) / PKT_WAVE * PKT_WAVE;
-  for (i64 g = (i64)blockIdx.x * PKT_BLOCK + threadIdx.x; g < total_up; g += (i64)gridDim.x * PKT_BLOCK) {
+  const i64 lim = total > nf ? total : (i64)nf;
+  const i64 lim_up = (lim + PKT_WAVE - 1) / PKT_WAVE * PKT_WAVE;  // whole waves stay in the loop
+  for (i64 g = (i64)blockIdx.x * PKT_BLOCK + threadIdx.x; g < lim_up; g += (i64)gridDim.x * PKT_BLOCK) {
+    if (g < nf) core[F[g]] = k;
     bool join = false;
     i32 v = -1;
     if (g < total) {
@@ -100,7 +145,7 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_kc_round(i32 n, i32 nf, const i32
       if (v < 0 || v >= n) {  // checked before any use as an index
         atomicOr(&cnt->err, 1u);
         v = -1;
-      } else if (core[v] < 0 && __hip_atomic_load(&deg[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > k) {
+      } else if (__hip_atomic_load(&deg[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > k) {
         const i32 old = atomicSub(&deg[v], 1);
         if (old == k + 1)
           join = true;
@@ -108,7 +153,7 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_kc_round(i32 n, i32 nf, const i32
           atomicAdd(&deg[v], 1);
       }
     }
-    const i32 s = wave_append_slot(join, &cnt->nnext);
+    const i32 s = wave_append_slot(join, &cnt->nnext[sel]);
     if (join) next[s] = v;
   }
 }
@@ -133,6 +178,28 @@ size_t kc_layout(i32 n, void* ws, KcWork* w) {
   t.cnt = cv.take<KcCounters>(1);
   if (w) *w = t;
   return cv.used;
+}
+
+// The counters come back through pinned host memory, one copy and one wait per
+// round; the buffer stays with the calling thread for its later calls.
+thread_local KcCounters* h_kc = nullptr;
+
+truss_status kc_read(const KcWork& w, KcCounters* out, hipStream_t s) {
+  if (!h_kc) PKT_HIP(hipHostMalloc((void**)&h_kc, sizeof(KcCounters), hipHostMallocDefault));
+  PKT_HIP(hipMemcpyAsync(h_kc, w.cnt, sizeof(KcCounters), hipMemcpyDeviceToHost, s));
+  PKT_HIP(hipStreamSynchronize(s));
+  *out = *h_kc;
+  return TRUSS_OK;
+}
+
+// Lanes for a round's items without reading their count back: a frontier vertex
+// at level k has at least k slots, and the average row length is the other
+// estimate; the grid-stride loop covers any count.
+inline int kc_round_grid(i32 nf, i32 k, i64 two_m, i32 n) {
+  const i64 avg = (two_m + n - 1) / n;
+  i64 est = (i64)nf * (k > avg ? (i64)k : avg);
+  if (est > two_m) est = two_m;
+  return kc_grid(est);
 }
 
 }  // namespace
@@ -176,29 +243,26 @@ extern "C" truss_status truss_kcore(int32_t n, const int64_t* offsets, const int
   hipLaunchKernelGGL(k_kc_init, dim3(kc_grid(n)), dim3(PKT_BLOCK), 0, s, n, two_m, offsets, w.deg, core, w.A[0],
                      w.cnt);
   PKT_LAUNCH_CHECK();
-  u32 err = 0;
-  PKT_HIP(hipMemcpyAsync(&err, &w.cnt->err, sizeof(u32), hipMemcpyDeviceToHost, s));
-  PKT_HIP(hipStreamSynchronize(s));
-  if (err) {
+  KcCounters hc;
+  if (truss_status st = kc_read(w, &hc, s)) return st;
+  if (hc.err) {
     set_error("input CSR: offsets out of order or past offsets[n]");
     return TRUSS_E_RANGE;
   }
   i32 na = n, asel = 0, k = 0, kmax = 0;
   i64 guard = 0;
-  KcCounters hc;
   while (na > 0) {
     if (++guard > (i64)n + 2) {  // every level either finds a vertex or jumps to a larger degree
       set_error("k-core level bound exceeded");
       return TRUSS_E_INTERNAL;
     }
     // level scan: the frontier and the vertices left
-    KcCounters z = {0, 0, INT_MAX, 0, 0, 0};
-    PKT_HIP(hipMemcpyAsync(w.cnt, &z, sizeof(z), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_kc_scan, dim3(kc_grid(na)), dim3(PKT_BLOCK), 0, s, na, (const i32*)w.A[asel], k,
-                       (const i32*)w.deg, w.F[0], w.A[asel ^ 1], w.cnt);
+    hipLaunchKernelGGL(k_kc_reset, dim3(1), dim3(1), 0, s, w.cnt);
+    const i64 tiles = ((i64)na + KC_TILE - 1) / KC_TILE;
+    hipLaunchKernelGGL(k_kc_scan, dim3((int)(tiles < 4096 ? tiles : 4096)), dim3(PKT_BLOCK), 0, s, na,
+                       (const i32*)w.A[asel], k, (const i32*)w.deg, w.F[0], w.A[asel ^ 1], w.cnt);
     PKT_LAUNCH_CHECK();
-    PKT_HIP(hipMemcpyAsync(&hc, w.cnt, sizeof(hc), hipMemcpyDeviceToHost, s));
-    PKT_HIP(hipStreamSynchronize(s));
+    if (truss_status st = kc_read(w, &hc, s)) return st;
     na = hc.nkeep;
     asel ^= 1;
     if (hc.nfound == 0) {
@@ -212,27 +276,18 @@ extern "C" truss_status truss_kcore(int32_t n, const int64_t* offsets, const int
         set_error("k-core round bound exceeded");
         return TRUSS_E_INTERNAL;
       }
-      hipLaunchKernelGGL(k_kc_mark, dim3(kc_grid(nf)), dim3(PKT_BLOCK), 0, s, nf, (const i32*)w.F[fsel], k, core);
       PKT_HIP(scan_launch(FrontierRows{w.F[fsel], offsets, nf}, w.partial, w.P, &w.cnt->arrive, s));
-      i64 items = 0;
-      PKT_HIP(hipMemcpyAsync(&items, w.P + nf, sizeof(i64), hipMemcpyDeviceToHost, s));
-      i32 zero = 0;
-      PKT_HIP(hipMemcpyAsync(&w.cnt->nnext, &zero, sizeof(i32), hipMemcpyHostToDevice, s));
-      PKT_HIP(hipStreamSynchronize(s));
-      if (items > 0)
-        hipLaunchKernelGGL(k_kc_round, dim3(kc_grid(items)), dim3(PKT_BLOCK), 0, s, n, nf, (const i32*)w.F[fsel],
-                           (const i64*)w.P, offsets, adj, k, (const i32*)core, w.deg, w.F[fsel ^ 1], w.cnt);
+      hipLaunchKernelGGL(k_kc_round, dim3(kc_round_grid(nf, k, two_m, n)), dim3(PKT_BLOCK), 0, s, n, nf,
+                         (const i32*)w.F[fsel], (const i64*)w.P, offsets, adj, k, core, w.deg, w.F[fsel ^ 1],
+                         fsel, w.cnt);
       PKT_LAUNCH_CHECK();
-      i32 nn = 0;
-      PKT_HIP(hipMemcpyAsync(&nn, &w.cnt->nnext, sizeof(i32), hipMemcpyDeviceToHost, s));
-      PKT_HIP(hipMemcpyAsync(&err, &w.cnt->err, sizeof(u32), hipMemcpyDeviceToHost, s));
-      PKT_HIP(hipStreamSynchronize(s));
-      if (err) {
+      if (truss_status st = kc_read(w, &hc, s)) return st;
+      if (hc.err) {
         set_error("input CSR: a neighbour id outside [0, n)");
         return TRUSS_E_RANGE;
       }
       kmax = k;
-      nf = nn;
+      nf = hc.nnext[fsel];
       fsel ^= 1;
     }
     k += 1;
