@@ -20,6 +20,9 @@ Contents
   * ``ktruss`` -- the maximal k-trusses given the trussness (Background section): the
     connected components of the edges of trussness >= k, each named by its smallest
     edge id.
+  * ``kco`` -- vertex reordering by increasing core number before support (Table 2's
+    KCO), the relabelled CSR, the trussness mapped back, and the work estimate
+    sum_v d+(v)^2.
   * ``psl_model`` -- a step-by-step model of the level-synchronous peeling
     (Algorithms 4 and 5 of the PKT section) whose threads interleave at random, to
     check the concurrency rules (lower-edge-id ownership, clamp and restore).
