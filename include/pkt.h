@@ -257,6 +257,61 @@ truss_status truss_kcore_workspace_bytes(int32_t n, size_t* bytes);
 truss_status truss_kcore(int32_t n, const int64_t* offsets, const int32_t* adj, int32_t* core, int32_t* max_core,
                          void* workspace, size_t workspace_bytes, void* stream);
 
+/* Vertex reordering by increasing core number (KCO; Experiments section, the
+ * support-computation study and Table 2): relabel the vertices so that ids grow
+ * with the core number, decompose the relabelled graph, and map its trussness back
+ * (the trussness of an edge does not depend on the labels).  Three calls, all on
+ * `stream` and all stream-ordered; each synchronises the stream a few times to
+ * check its inputs.  The caller owns every buffer.
+ *
+ * truss_kco_order: the new id of every vertex, sorted by (core number, old id).
+ *   n                vertices (>= 0)
+ *   core             device, int32[n]: core numbers (truss_kcore), each >= 0
+ *   new_id           device, int32[n] out: new id of old vertex v
+ *   order            device, int32[n] out: old vertex at new id i (the inverse)
+ *   workspace        device, truss_kco_order_workspace_bytes(n) bytes, 256-byte aligned
+ * Errors: TRUSS_E_ARG, TRUSS_E_RANGE (a negative core number), TRUSS_E_WORKSPACE,
+ * TRUSS_E_DEVICE.
+ *
+ * truss_kco_relabel: the CSR of the relabelled graph, every row sorted.
+ *   offsets, adj     device, the input: a symmetric CSR as for truss_decompose
+ *                    (int64[n+1] starting at 0, int32[2m])
+ *   new_id, order    device, int32[n]: a permutation and its inverse (truss_kco_order)
+ *   offsets2         device, int64[n+1] out
+ *   adj2             device, int32[2m] out (NULL when m = 0)
+ *   workspace        device, truss_kco_relabel_workspace_bytes(n, 2m) bytes (about
+ *                    16 bytes per adjacency slot), 256-byte aligned
+ * Errors: TRUSS_E_ARG (NULL buffers, or 2m beyond 2^34 slots), TRUSS_E_RANGE
+ * (offsets not starting at 0 or out of order, a neighbour outside [0, n), new_id
+ * not a permutation with order its inverse, or a CSR that is not symmetric; the
+ * outputs are then undefined), TRUSS_E_WORKSPACE, TRUSS_E_DEVICE.
+ *
+ * truss_kco_map: trussness per input edge from the trussness of the relabelled graph.
+ *   n, m             vertices and edges of the input
+ *   el_u, el_v       device, int32[m]: the input's edges (any order; truss_edge_list
+ *                    gives the canonical one, so that the output is indexed by the
+ *                    input's edge ids)
+ *   new_id           device, int32[n]: as given to truss_kco_relabel
+ *   offsets2, adj2   device: its output
+ *   trussness2       device, int32[m]: truss_decompose of the relabelled graph
+ *   trussness        device, int32[m] out: trussness of edge (el_u[e], el_v[e])
+ *   workspace        device, truss_kco_map_workspace_bytes(n) bytes, 256-byte aligned
+ * Errors: TRUSS_E_ARG (offsets2[n] != 2m, NULL buffers), TRUSS_E_RANGE (offsets2 out
+ * of order, a new id or an endpoint outside [0, n), an edge with no image in the
+ * relabelled graph; its entry is then -1), TRUSS_E_WORKSPACE, TRUSS_E_DEVICE.
+ */
+truss_status truss_kco_order_workspace_bytes(int32_t n, size_t* bytes);
+truss_status truss_kco_order(int32_t n, const int32_t* core, int32_t* new_id, int32_t* order, void* workspace,
+                             size_t workspace_bytes, void* stream);
+truss_status truss_kco_relabel_workspace_bytes(int32_t n, int64_t two_m, size_t* bytes);
+truss_status truss_kco_relabel(int32_t n, const int64_t* offsets, const int32_t* adj, const int32_t* new_id,
+                               const int32_t* order, int64_t* offsets2, int32_t* adj2, void* workspace,
+                               size_t workspace_bytes, void* stream);
+truss_status truss_kco_map_workspace_bytes(int32_t n, size_t* bytes);
+truss_status truss_kco_map(int32_t n, int64_t m, const int32_t* el_u, const int32_t* el_v, const int32_t* new_id,
+                           const int64_t* offsets2, const int32_t* adj2, const int32_t* trussness2,
+                           int32_t* trussness, void* workspace, size_t workspace_bytes, void* stream);
+
 /*
  * Batched decomposition of many independent graphs.  By default they are
  * decomposed together as one disjoint union (one level loop and one launch

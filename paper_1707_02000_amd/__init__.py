@@ -134,6 +134,14 @@ _SIGS = {
                         + [ctypes.c_void_p]),
     "truss_ktruss_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p]),
     "truss_kcore_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p]),
+    "truss_kco_order_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p]),
+    "truss_kco_order": (ctypes.c_int, [ctypes.c_int32] + [ctypes.c_void_p] * 4 + [ctypes.c_size_t, ctypes.c_void_p]),
+    "truss_kco_relabel_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p]),
+    "truss_kco_relabel": (ctypes.c_int, [ctypes.c_int32] + [ctypes.c_void_p] * 7
+                          + [ctypes.c_size_t, ctypes.c_void_p]),
+    "truss_kco_map_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p]),
+    "truss_kco_map": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64] + [ctypes.c_void_p] * 8
+                      + [ctypes.c_size_t, ctypes.c_void_p]),
     "truss_kcore": (ctypes.c_int, [ctypes.c_int32] + [ctypes.c_void_p] * 5 + [ctypes.c_size_t, ctypes.c_void_p]),
     "truss_ktruss": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64] + [ctypes.c_void_p] * 3 + [ctypes.c_int32]
                      + [ctypes.c_void_p] * 3 + [ctypes.c_size_t, ctypes.c_void_p]),
@@ -393,6 +401,69 @@ def kcore(offsets, adj, *, stream=None):
     _check(lib.truss_kcore(int(n), _ptr(off_t), _ptr(adj_t), _ptr(out), ctypes.byref(cmax), ctypes.c_void_p(wptr),
                            nb.value, _stream(torch, stream)))
     return out[:n], int(cmax.value)
+
+
+def kco_order(core, *, stream=None):
+    """KCO order: (new_id, order) int32 [n] CUDA tensors, vertices sorted by (core number, id)."""
+    torch = _torch()
+    lib = load()
+    c = _dev(core, torch.int32, torch)
+    n = c.numel()
+    nb = ctypes.c_size_t(0)
+    _check(lib.truss_kco_order_workspace_bytes(int(n), ctypes.byref(nb)))
+    _buf, wptr = alloc_workspace(nb.value)
+    new_id = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+    order = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+    _check(lib.truss_kco_order(int(n), _ptr(c), _ptr(new_id), _ptr(order), ctypes.c_void_p(wptr), nb.value,
+                               _stream(torch, stream)))
+    return new_id[:n], order[:n]
+
+
+def kco_relabel(offsets, adj, new_id, order, *, stream=None):
+    """The relabelled CSR (offsets2 int64 [n+1], adj2 int32 [2m] CUDA tensors), rows sorted."""
+    torch = _torch()
+    lib = load()
+    off_t = _dev(offsets, torch.int64, torch)
+    adj_t = _dev(adj, torch.int32, torch)
+    nid = _dev(new_id, torch.int32, torch)
+    ordr = _dev(order, torch.int32, torch)
+    n = off_t.numel() - 1
+    two_m = adj_t.numel()
+    nb = ctypes.c_size_t(0)
+    _check(lib.truss_kco_relabel_workspace_bytes(int(n), int(two_m), ctypes.byref(nb)))
+    _buf, wptr = alloc_workspace(nb.value)
+    off2 = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    adj2 = torch.empty(max(two_m, 1), dtype=torch.int32, device="cuda")
+    _check(lib.truss_kco_relabel(int(n), _ptr(off_t), _ptr(adj_t), _ptr(nid), _ptr(ordr), _ptr(off2),
+                                 _ptr(adj2) if two_m else ctypes.c_void_p(0), ctypes.c_void_p(wptr), nb.value,
+                                 _stream(torch, stream)))
+    return off2, adj2[:two_m]
+
+
+def kco_map(n, edges, new_id, offsets2, adj2, trussness2, *, stream=None):
+    """Trussness per input edge (int32 [m] CUDA tensor) from that of the relabelled graph.
+
+    edges: (m, 2) int32 endpoints of the input (as from edge_list) or a pair of int32 [m] arrays.
+    """
+    torch = _torch()
+    lib = load()
+    if isinstance(edges, (tuple, list)):
+        eu, ev = (_dev(x, torch.int32, torch).contiguous() for x in edges)
+    else:
+        e = _dev(edges, torch.int32, torch).reshape(-1, 2)
+        eu, ev = e[:, 0].contiguous(), e[:, 1].contiguous()
+    nid = _dev(new_id, torch.int32, torch)
+    off2 = _dev(offsets2, torch.int64, torch)
+    adj2 = _dev(adj2, torch.int32, torch)
+    tau2 = _dev(trussness2, torch.int32, torch)
+    m = eu.numel()
+    nb = ctypes.c_size_t(0)
+    _check(lib.truss_kco_map_workspace_bytes(int(n), ctypes.byref(nb)))
+    _buf, wptr = alloc_workspace(nb.value)
+    out = torch.empty(max(m, 1), dtype=torch.int32, device="cuda")
+    _check(lib.truss_kco_map(int(n), int(m), _ptr(eu), _ptr(ev), _ptr(nid), _ptr(off2), _ptr(adj2), _ptr(tau2),
+                             _ptr(out), ctypes.c_void_p(wptr), nb.value, _stream(torch, stream)))
+    return out[:m]
 
 
 def truss_decompose_batched(vtx_off, adj_off, offsets_packed, adj_packed, *, variant="auto", validate=True,

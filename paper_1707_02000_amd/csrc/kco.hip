@@ -1,0 +1,522 @@
+// Vertex reordering by increasing core number (KCO) before support, as in the
+// support-computation study of the Experiments section (Table 2): the new ids
+// sort vertices by core number (ties by old id), the relabelled CSR keeps every
+// row sorted, and the trussness computed on the relabelled graph is mapped back to
+// the input's edge ids (trussness does not depend on the labels).
+//
+// Both sorts are one stable LSD radix sort of (u32 key, i32 value) pairs, eight
+// key bits per pass.  A block ranks its tile of RS_TILE pairs stably by digit (a
+// wave finds its lanes of equal digit with eight ballots; earlier sub-steps, then
+// lower waves, then lower lanes come first) and writes the tile's digit counts
+// into a digit-major matrix; the device prefix of that matrix (scan.h) gives every
+// (digit, tile) its first place, and a second pass over the tile scatters.  The
+// order sorts (core, v) by core; the relabelled CSR sorts (new row, new neighbour)
+// pairs, produced in increasing order of the neighbour, by row, which leaves every
+// row sorted.
+#include <limits.h>
+
+#include "common.h"
+#include "scan.h"
+
+namespace {
+
+constexpr int RS_BINS = 256;
+constexpr int RS_ITEMS = 4;
+constexpr int RS_TILE = RS_ITEMS * PKT_BLOCK;
+constexpr int RS_WAVES = PKT_BLOCK / PKT_WAVE;
+static_assert(PKT_BLOCK == RS_BINS, "one thread per digit");
+
+inline int ko_grid(i64 count) {
+  const i64 g = (count + PKT_BLOCK - 1) / PKT_BLOCK;
+  return (int)(g < 1 ? 1 : (g > 8192 ? 8192 : g));
+}
+
+inline i64 rs_tiles(i64 cnt) { return (cnt + RS_TILE - 1) / RS_TILE; }
+
+inline int bit_width(i64 x) {
+  int b = 0;
+  while (x > 0) {
+    ++b;
+    x >>= 1;
+  }
+  return b;
+}
+
+// One radix pass over tile blockIdx.x: without SCATTER the tile's digit counts go
+// to hist[digit * tiles + tile]; with it every pair goes to start[digit * tiles +
+// tile] + its stable rank among the tile's pairs of that digit.
+template <bool SCATTER>
+__global__ __launch_bounds__(PKT_BLOCK) void k_rs_pass(i64 cnt, i64 tiles, const u32* __restrict__ keys,
+                                                      const i32* __restrict__ vals, int shift, i32* __restrict__ hist,
+                                                      const i64* __restrict__ start, u32* __restrict__ okeys,
+                                                      i32* __restrict__ ovals) {
+  __shared__ i32 wc[RS_WAVES][RS_BINS];  // this sub-step's count per wave and digit
+  __shared__ i32 run[RS_BINS];           // the tile's count per digit before this sub-step
+  __shared__ i64 base[RS_BINS];
+  const int tid = threadIdx.x, wid = tid / PKT_WAVE, lane = lane_id();
+  const i64 t = blockIdx.x;
+  run[tid] = 0;
+  for (int w = 0; w < RS_WAVES; ++w) wc[w][tid] = 0;
+  if (SCATTER) base[tid] = start[(i64)tid * tiles + t];
+  __syncthreads();
+  const u64 below = (1ull << lane) - 1ull;
+  for (int sub = 0; sub < RS_ITEMS; ++sub) {
+    const i64 i = t * RS_TILE + (i64)sub * PKT_BLOCK + tid;
+    const bool valid = i < cnt;
+    const u32 key = valid ? keys[i] : 0u;
+    const int d = (int)((key >> shift) & (u32)(RS_BINS - 1));
+    u64 same = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1;
+      const u64 bb = __ballot(bit);
+      same &= bit ? bb : ~bb;
+    }
+    const int lower = __popcll(same & below);
+    if (valid && lower == 0) wc[wid][d] = __popcll(same);
+    __syncthreads();
+    if (SCATTER && valid) {
+      i32 r = run[d] + lower;
+      for (int w = 0; w < wid; ++w) r += wc[w][d];
+      const i64 pos = base[d] + r;
+      okeys[pos] = key;
+      ovals[pos] = vals[i];
+    }
+    __syncthreads();
+    i32 tot = 0;
+    for (int w = 0; w < RS_WAVES; ++w) {
+      tot += wc[w][tid];
+      wc[w][tid] = 0;
+    }
+    run[tid] += tot;
+    __syncthreads();
+  }
+  if (!SCATTER) hist[(i64)tid * tiles + t] = run[tid];
+}
+
+struct HistLen {
+  const i32* h;
+  i64 n;
+  __device__ bool active() const { return true; }
+  __device__ i64 count() const { return n; }
+  __device__ i64 len(i64 i) const { return h[i]; }
+};
+
+struct RsBufs {
+  u32* k[2];
+  i32* v[2];
+  i32* hist;
+  i64* start;
+  i64* partial;
+  u32* arrive;  // zeroed before the first pass; the prefix leaves it zeroed
+};
+
+void rs_take(Carver& cv, i64 cnt, RsBufs* b) {
+  const i64 cells = rs_tiles(cnt) * RS_BINS;
+  for (int q = 0; q < 2; ++q) b->k[q] = cv.take<u32>((size_t)cnt);
+  for (int q = 0; q < 2; ++q) b->v[q] = cv.take<i32>((size_t)cnt);
+  b->hist = cv.take<i32>((size_t)cells);
+  b->start = cv.take<i64>((size_t)cells + 1);
+  b->partial = cv.take<i64>(SCAN_BLOCKS + 1);
+  b->arrive = cv.take<u32>(1);
+}
+
+// Sorts the cnt pairs in k[0], v[0] stably by their low `bits` key bits; *sel is
+// the buffer that holds the result.
+truss_status rs_sort(i64 cnt, int bits, const RsBufs& b, hipStream_t s, int* sel) {
+  int q = 0;
+  if (cnt > 0) {
+    const i64 tiles = rs_tiles(cnt);
+    if (tiles >= ((i64)1 << 24)) {  // a launch holds fewer than 2^32 work-items
+      pkt::set_error("radix sort of %lld pairs: too many", (long long)cnt);
+      return TRUSS_E_ARG;
+    }
+    for (int shift = 0; shift < bits; shift += 8) {
+      hipLaunchKernelGGL(k_rs_pass<false>, dim3((unsigned)tiles), dim3(PKT_BLOCK), 0, s, cnt, tiles,
+                         (const u32*)b.k[q], (const i32*)b.v[q], shift, b.hist, (const i64*)nullptr,
+                         (u32*)nullptr, (i32*)nullptr);
+      PKT_HIP(scan_launch(HistLen{b.hist, tiles * RS_BINS}, b.partial, b.start, b.arrive, s));
+      hipLaunchKernelGGL(k_rs_pass<true>, dim3((unsigned)tiles), dim3(PKT_BLOCK), 0, s, cnt, tiles,
+                         (const u32*)b.k[q], (const i32*)b.v[q], shift, (i32*)nullptr, (const i64*)b.start,
+                         b.k[q ^ 1], b.v[q ^ 1]);
+      PKT_LAUNCH_CHECK();
+      q ^= 1;
+    }
+  }
+  *sel = q;
+  return TRUSS_OK;
+}
+
+struct KoFlags {
+  u32 err;
+  i32 kmax;
+};
+
+truss_status read_flags(const KoFlags* d, KoFlags* h, hipStream_t s) {
+  PKT_HIP(hipMemcpyAsync(h, d, sizeof(KoFlags), hipMemcpyDeviceToHost, s));
+  PKT_HIP(hipStreamSynchronize(s));
+  return TRUSS_OK;
+}
+
+// ---------------------------------------------------------------- the order
+
+__global__ __launch_bounds__(PKT_BLOCK) void k_ko_init(i32 n, const i32* __restrict__ core, u32* __restrict__ keys,
+                                                      i32* __restrict__ vals, KoFlags* fl) {
+  i32 mx = 0;
+  const i64 n_up = ((i64)n + PKT_WAVE - 1) / PKT_WAVE * PKT_WAVE;  // whole waves stay in the loop
+  for (i64 v = (i64)blockIdx.x * PKT_BLOCK + threadIdx.x; v < n_up; v += (i64)gridDim.x * PKT_BLOCK) {
+    if (v < n) {
+      const i32 c = core[v];
+      if (c < 0) atomicOr(&fl->err, 1u);
+      keys[v] = (u32)(c < 0 ? 0 : c);
+      vals[v] = (i32)v;
+      mx = max(mx, c);
+    }
+  }
+  mx = wave_max_i32(mx);
+  if (lane_id() == 0 && mx > 0) atomicMax(&fl->kmax, mx);
+}
+
+__global__ __launch_bounds__(PKT_BLOCK) void k_ko_out(i32 n, const i32* __restrict__ sorted, i32* __restrict__ order,
+                                                     i32* __restrict__ new_id, KoFlags* fl) {
+  for (i64 i = (i64)blockIdx.x * PKT_BLOCK + threadIdx.x; i < n; i += (i64)gridDim.x * PKT_BLOCK) {
+    const i32 v = sorted[i];  // a permutation of 0..n-1: the values start as the ids
+    order[i] = v;
+    if (v >= 0 && v < n)
+      new_id[v] = (i32)i;
+    else
+      atomicOr(&fl->err, 2u);
+  }
+}
+
+size_t ko_layout(i32 n, void* ws, RsBufs* b, KoFlags** fl) {
+  Carver cv(ws);
+  RsBufs t;
+  rs_take(cv, n, &t);
+  KoFlags* f = cv.take<KoFlags>(1);
+  if (b) *b = t;
+  if (fl) *fl = f;
+  return cv.used;
+}
+
+// ------------------------------------------------------ the relabelled CSR
+
+// Offsets in order and inside the adjacency, and new_id a permutation with
+// order its inverse: order[new_id[v]] == v for every v (new_id is read as an
+// index only after its range check).
+__global__ __launch_bounds__(PKT_BLOCK) void k_rl_check(i32 n, i64 two_m, const i64* __restrict__ off,
+                                                       const i32* __restrict__ new_id, const i32* __restrict__ order,
+                                                       KoFlags* fl) {
+  for (i64 v = (i64)blockIdx.x * PKT_BLOCK + threadIdx.x; v < n; v += (i64)gridDim.x * PKT_BLOCK) {
+    const i64 b = off[v], e = off[v + 1];
+    if ((v == 0 && b != 0) || b < 0 || e < b || e > two_m) atomicOr(&fl->err, 1u);
+    const i32 x = new_id[v];
+    if (x < 0 || x >= n || order[x] != (i32)v) atomicOr(&fl->err, 2u);
+  }
+}
+
+// Row length of new vertex y: the degree of the old vertex order[y].
+struct RelabelRows {
+  const i32* order;
+  const i64* off;
+  i32 n;
+  __device__ bool active() const { return true; }
+  __device__ i64 count() const { return n; }
+  __device__ i64 len(i64 y) const {
+    const i32 u = order[y];
+    return off[u + 1] - off[u];
+  }
+};
+
+// Slot j of old row u becomes the pair (new_id[adj[j]], new_id[u]) at place
+// off2[new_id[u]] + (j - off[u]): grouped by the new id of u, increasing.
+__global__ __launch_bounds__(PKT_BLOCK) void k_rl_pairs(i32 n, i64 two_m, const i64* __restrict__ off,
+                                                       const i32* __restrict__ adj, const i32* __restrict__ new_id,
+                                                       const i64* __restrict__ off2, u32* __restrict__ keys,
+                                                       i32* __restrict__ vals, KoFlags* fl) {
+  for (i64 j = (i64)blockIdx.x * PKT_BLOCK + threadIdx.x; j < two_m; j += (i64)gridDim.x * PKT_BLOCK) {
+    const i32 u = (i32)(upper_bound_dev(off, (i64)0, (i64)n + 1, j) - 1);
+    const i32 w = adj[j];
+    if (w < 0 || w >= n) {  // checked before any use as an index
+      atomicOr(&fl->err, 4u);
+      continue;
+    }
+    const i32 y = new_id[u];
+    const i64 pos = off2[y] + (j - off[u]);
+    keys[pos] = (u32)new_id[w];
+    vals[pos] = y;
+  }
+}
+
+// Row x of the sorted pairs starts where off2 says: true of every symmetric CSR.
+__global__ __launch_bounds__(PKT_BLOCK) void k_rl_rows(i32 n, i64 two_m, const u32* __restrict__ keys,
+                                                      const i64* __restrict__ off2, KoFlags* fl) {
+  for (i64 x = (i64)blockIdx.x * PKT_BLOCK + threadIdx.x; x < n; x += (i64)gridDim.x * PKT_BLOCK)
+    if (lower_bound_dev(keys, (i64)0, two_m, (u32)x) != off2[x]) atomicOr(&fl->err, 8u);
+}
+
+size_t rl_layout(i64 two_m, void* ws, RsBufs* b, KoFlags** fl) {
+  Carver cv(ws);
+  RsBufs t;
+  rs_take(cv, two_m, &t);
+  KoFlags* f = cv.take<KoFlags>(1);
+  if (b) *b = t;
+  if (fl) *fl = f;
+  return cv.used;
+}
+
+// ---------------------------------------------------------------- mapping back
+
+__global__ __launch_bounds__(PKT_BLOCK) void k_map_check(i32 n, i64 two_m, const i64* __restrict__ off2,
+                                                        const i32* __restrict__ new_id, KoFlags* fl) {
+  for (i64 v = (i64)blockIdx.x * PKT_BLOCK + threadIdx.x; v < n; v += (i64)gridDim.x * PKT_BLOCK) {
+    const i64 b = off2[v], e = off2[v + 1];
+    if ((v == 0 && b != 0) || b < 0 || e < b || e > two_m) atomicOr(&fl->err, 1u);
+    const i32 x = new_id[v];
+    if (x < 0 || x >= n) atomicOr(&fl->err, 2u);
+  }
+}
+
+// Canonical edges of row x of the relabelled graph: its entries above x.
+struct UpperRows {
+  const i64* off2;
+  const i32* adj2;
+  i32 n;
+  __device__ bool active() const { return true; }
+  __device__ i64 count() const { return n; }
+  __device__ i64 len(i64 x) const { return off2[x + 1] - upper_bound_dev(adj2, off2[x], off2[x + 1], (i32)x); }
+};
+
+// tau[e] = tau2[edge id of (new_id[u], new_id[v]) in the relabelled graph]: the
+// canonical edges of the rows before a, then the rank of b among row a's entries
+// above a.
+__global__ __launch_bounds__(PKT_BLOCK) void k_map(i32 n, i64 m, const i32* __restrict__ eu,
+                                                  const i32* __restrict__ ev, const i32* __restrict__ new_id,
+                                                  const i64* __restrict__ off2, const i32* __restrict__ adj2,
+                                                  const i64* __restrict__ U, const i32* __restrict__ tau2,
+                                                  i32* __restrict__ tau, KoFlags* fl) {
+  for (i64 e = (i64)blockIdx.x * PKT_BLOCK + threadIdx.x; e < m; e += (i64)gridDim.x * PKT_BLOCK) {
+    const i32 u = eu[e], v = ev[e];
+    i32 t = -1;
+    if (u < 0 || u >= n || v < 0 || v >= n) {
+      atomicOr(&fl->err, 4u);
+    } else {
+      const i32 x = new_id[u], y = new_id[v];
+      const i32 a = min(x, y), b = max(x, y);
+      const i64 end = off2[a + 1];
+      const i64 fa = upper_bound_dev(adj2, off2[a], end, a);
+      const i64 pos = lower_bound_dev(adj2, fa, end, b);
+      const i64 id = U[a] + (pos - fa);
+      if (a == b || pos == end || adj2[pos] != b || id >= m)
+        atomicOr(&fl->err, 8u);
+      else
+        t = tau2[id];
+    }
+    tau[e] = t;
+  }
+}
+
+size_t map_layout(i32 n, void* ws, i64** U, i64** partial, u32** arrive, KoFlags** fl) {
+  Carver cv(ws);
+  i64* u = cv.take<i64>((size_t)n + 1);
+  i64* p = cv.take<i64>(SCAN_BLOCKS + 1);
+  u32* a = cv.take<u32>(1);
+  KoFlags* f = cv.take<KoFlags>(1);
+  if (U) *U = u;
+  if (partial) *partial = p;
+  if (arrive) *arrive = a;
+  if (fl) *fl = f;
+  return cv.used;
+}
+
+bool ws_ok(void* ws, size_t bytes, size_t need) {
+  if (ws == nullptr || bytes < need || ((uintptr_t)ws & 255u)) {
+    pkt::set_error("workspace: need %zu bytes at 256-byte alignment", need);
+    return false;
+  }
+  return true;
+}
+
+}  // namespace
+
+extern "C" truss_status truss_kco_order_workspace_bytes(int32_t n, size_t* bytes) {
+  pkt::set_error("");
+  if (n < 0 || bytes == nullptr) {
+    pkt::set_error("bad arguments to truss_kco_order_workspace_bytes");
+    return TRUSS_E_ARG;
+  }
+  *bytes = ko_layout(n, nullptr, nullptr, nullptr);
+  return TRUSS_OK;
+}
+
+extern "C" truss_status truss_kco_order(int32_t n, const int32_t* core, int32_t* new_id, int32_t* order,
+                                        void* workspace, size_t workspace_bytes, void* stream) {
+  using namespace pkt;
+  set_error("");
+  if (n < 0 || (n > 0 && (core == nullptr || new_id == nullptr || order == nullptr))) {
+    set_error("bad n or NULL core / new_id / order");
+    return TRUSS_E_ARG;
+  }
+  if (!ws_ok(workspace, workspace_bytes, ko_layout(n, nullptr, nullptr, nullptr))) return TRUSS_E_WORKSPACE;
+  if (n == 0) return TRUSS_OK;
+  hipStream_t s = (hipStream_t)stream;
+  RsBufs b;
+  KoFlags* fl;
+  ko_layout(n, workspace, &b, &fl);
+  PKT_HIP(hipMemsetAsync(fl, 0, sizeof(KoFlags), s));
+  PKT_HIP(hipMemsetAsync(b.arrive, 0, sizeof(u32), s));
+  hipLaunchKernelGGL(k_ko_init, dim3(ko_grid(n)), dim3(PKT_BLOCK), 0, s, n, core, b.k[0], b.v[0], fl);
+  PKT_LAUNCH_CHECK();
+  KoFlags h;
+  if (truss_status st = read_flags(fl, &h, s)) return st;
+  if (h.err) {
+    set_error("a negative core number");
+    return TRUSS_E_RANGE;
+  }
+  int q = 0;
+  if (truss_status st = rs_sort(n, bit_width(h.kmax), b, s, &q)) return st;
+  hipLaunchKernelGGL(k_ko_out, dim3(ko_grid(n)), dim3(PKT_BLOCK), 0, s, n, (const i32*)b.v[q], order, new_id, fl);
+  PKT_LAUNCH_CHECK();
+  if (truss_status st = read_flags(fl, &h, s)) return st;
+  if (h.err) {
+    set_error("radix sort: output is not a permutation");
+    return TRUSS_E_INTERNAL;
+  }
+  return TRUSS_OK;
+}
+
+extern "C" truss_status truss_kco_relabel_workspace_bytes(int32_t n, int64_t two_m, size_t* bytes) {
+  pkt::set_error("");
+  if (n < 0 || two_m < 0 || bytes == nullptr) {
+    pkt::set_error("bad arguments to truss_kco_relabel_workspace_bytes");
+    return TRUSS_E_ARG;
+  }
+  *bytes = rl_layout(two_m, nullptr, nullptr, nullptr);
+  return TRUSS_OK;
+}
+
+extern "C" truss_status truss_kco_relabel(int32_t n, const int64_t* offsets, const int32_t* adj, const int32_t* new_id,
+                                          const int32_t* order, int64_t* offsets2, int32_t* adj2, void* workspace,
+                                          size_t workspace_bytes, void* stream) {
+  using namespace pkt;
+  set_error("");
+  if (n < 0 || (n > 0 && (offsets == nullptr || new_id == nullptr || order == nullptr)) || offsets2 == nullptr) {
+    set_error("bad n or NULL offsets / new_id / order / offsets2");
+    return TRUSS_E_ARG;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  i64 two_m = 0;
+  if (n > 0) {
+    PKT_HIP(hipMemcpyAsync(&two_m, offsets + n, sizeof(i64), hipMemcpyDeviceToHost, s));
+    PKT_HIP(hipStreamSynchronize(s));
+  }
+  if (two_m < 0 || two_m > ((i64)1 << 40)) {
+    set_error("offsets[n] = %lld is out of range", (long long)two_m);
+    return TRUSS_E_RANGE;
+  }
+  if (two_m > 0 && (adj == nullptr || adj2 == nullptr)) {
+    set_error("NULL adj / adj2");
+    return TRUSS_E_ARG;
+  }
+  if (!ws_ok(workspace, workspace_bytes, rl_layout(two_m, nullptr, nullptr, nullptr))) return TRUSS_E_WORKSPACE;
+  if (n == 0) {
+    PKT_HIP(hipMemsetAsync(offsets2, 0, sizeof(i64), s));
+    return TRUSS_OK;
+  }
+  RsBufs b;
+  KoFlags* fl;
+  rl_layout(two_m, workspace, &b, &fl);
+  PKT_HIP(hipMemsetAsync(fl, 0, sizeof(KoFlags), s));
+  PKT_HIP(hipMemsetAsync(b.arrive, 0, sizeof(u32), s));
+  hipLaunchKernelGGL(k_rl_check, dim3(ko_grid(n)), dim3(PKT_BLOCK), 0, s, n, two_m, offsets, new_id, order, fl);
+  PKT_LAUNCH_CHECK();
+  KoFlags h;
+  if (truss_status st = read_flags(fl, &h, s)) return st;
+  if (h.err) {
+    set_error(h.err & 1u ? "input CSR: offsets not starting at 0, out of order or past offsets[n]"
+                         : "new_id is not a permutation with order its inverse");
+    return TRUSS_E_RANGE;
+  }
+  PKT_HIP(scan_launch(RelabelRows{order, offsets, n}, b.partial, offsets2, b.arrive, s));
+  hipLaunchKernelGGL(k_rl_pairs, dim3(ko_grid(two_m)), dim3(PKT_BLOCK), 0, s, n, two_m, offsets, adj, new_id,
+                     (const i64*)offsets2, b.k[0], b.v[0], fl);
+  PKT_LAUNCH_CHECK();
+  if (truss_status st = read_flags(fl, &h, s)) return st;
+  if (h.err) {
+    set_error("input CSR: a neighbour id outside [0, n)");
+    return TRUSS_E_RANGE;
+  }
+  int q = 0;
+  if (truss_status st = rs_sort(two_m, bit_width((i64)n - 1), b, s, &q)) return st;
+  hipLaunchKernelGGL(k_rl_rows, dim3(ko_grid(n)), dim3(PKT_BLOCK), 0, s, n, two_m, (const u32*)b.k[q],
+                     (const i64*)offsets2, fl);
+  PKT_LAUNCH_CHECK();
+  if (two_m > 0) PKT_HIP(hipMemcpyAsync(adj2, b.v[q], sizeof(i32) * (size_t)two_m, hipMemcpyDeviceToDevice, s));
+  if (truss_status st = read_flags(fl, &h, s)) return st;
+  if (h.err) {
+    set_error("input CSR is not symmetric");
+    return TRUSS_E_RANGE;
+  }
+  return TRUSS_OK;
+}
+
+extern "C" truss_status truss_kco_map_workspace_bytes(int32_t n, size_t* bytes) {
+  pkt::set_error("");
+  if (n < 0 || bytes == nullptr) {
+    pkt::set_error("bad arguments to truss_kco_map_workspace_bytes");
+    return TRUSS_E_ARG;
+  }
+  *bytes = map_layout(n, nullptr, nullptr, nullptr, nullptr, nullptr);
+  return TRUSS_OK;
+}
+
+extern "C" truss_status truss_kco_map(int32_t n, int64_t m, const int32_t* el_u, const int32_t* el_v,
+                                      const int32_t* new_id, const int64_t* offsets2, const int32_t* adj2,
+                                      const int32_t* trussness2, int32_t* trussness, void* workspace,
+                                      size_t workspace_bytes, void* stream) {
+  using namespace pkt;
+  set_error("");
+  if (n < 0 || m < 0 || (n > 0 && (new_id == nullptr || offsets2 == nullptr)) ||
+      (m > 0 && (n == 0 || el_u == nullptr || el_v == nullptr || adj2 == nullptr || trussness2 == nullptr ||
+                 trussness == nullptr))) {
+    set_error("bad n, m or a NULL argument");
+    return TRUSS_E_ARG;
+  }
+  if (!ws_ok(workspace, workspace_bytes, map_layout(n, nullptr, nullptr, nullptr, nullptr, nullptr)))
+    return TRUSS_E_WORKSPACE;
+  if (m == 0) return TRUSS_OK;
+  hipStream_t s = (hipStream_t)stream;
+  i64 two_m = 0;
+  PKT_HIP(hipMemcpyAsync(&two_m, offsets2 + n, sizeof(i64), hipMemcpyDeviceToHost, s));
+  PKT_HIP(hipStreamSynchronize(s));
+  if (two_m != 2 * m) {
+    set_error("offsets2[n] = %lld, not 2m = %lld", (long long)two_m, (long long)(2 * m));
+    return TRUSS_E_ARG;
+  }
+  i64 *U, *partial;
+  u32* arrive;
+  KoFlags* fl;
+  map_layout(n, workspace, &U, &partial, &arrive, &fl);
+  PKT_HIP(hipMemsetAsync(fl, 0, sizeof(KoFlags), s));
+  PKT_HIP(hipMemsetAsync(arrive, 0, sizeof(u32), s));
+  hipLaunchKernelGGL(k_map_check, dim3(ko_grid(n)), dim3(PKT_BLOCK), 0, s, n, two_m, offsets2, new_id, fl);
+  PKT_LAUNCH_CHECK();
+  KoFlags h;
+  if (truss_status st = read_flags(fl, &h, s)) return st;
+  if (h.err) {
+    set_error(h.err & 1u ? "relabelled CSR: offsets not starting at 0, out of order or past offsets2[n]"
+                         : "new_id: a value outside [0, n)");
+    return TRUSS_E_RANGE;
+  }
+  PKT_HIP((scan_launch<UpperRows, true>(UpperRows{offsets2, adj2, n}, partial, U, arrive, s)));
+  hipLaunchKernelGGL(k_map, dim3(ko_grid(m)), dim3(PKT_BLOCK), 0, s, n, (i64)m, el_u, el_v, new_id, offsets2, adj2,
+                     (const i64*)U, trussness2, trussness, fl);
+  PKT_LAUNCH_CHECK();
+  if (truss_status st = read_flags(fl, &h, s)) return st;
+  if (h.err) {
+    set_error(h.err & 4u ? "edge list: an endpoint outside [0, n)"
+                         : "an input edge has no image in the relabelled graph");
+    return TRUSS_E_RANGE;
+  }
+  return TRUSS_OK;
+}
