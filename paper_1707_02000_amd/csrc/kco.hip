@@ -7,9 +7,10 @@
 // Both sorts are one stable LSD radix sort of (u32 key, i32 value) pairs, eight
 // key bits per pass.  A block ranks its tile of RS_TILE pairs stably by digit (a
 // wave finds its lanes of equal digit with eight ballots; earlier sub-steps, then
-// lower waves, then lower lanes come first) and writes the tile's digit counts
-// into a digit-major matrix; the device prefix of that matrix (scan.h) gives every
-// (digit, tile) its first place, and a second pass over the tile scatters.  The
+// lower waves, then lower lanes come first): a first pass writes the tile's digit
+// counts into a digit-major matrix, the device prefix of that matrix (scan.h)
+// gives every (digit, tile) its first place, and a second pass stages the tile in
+// LDS in digit order and writes it out in runs of consecutive places.  The
 // order sorts (core, v) by core; the relabelled CSR sorts (new row, new neighbour)
 // pairs, produced in increasing order of the neighbour, by row, which leaves every
 // row sorted.
@@ -21,7 +22,7 @@
 namespace {
 
 constexpr int RS_BINS = 256;
-constexpr int RS_ITEMS = 4;
+constexpr int RS_ITEMS = 8;
 constexpr int RS_TILE = RS_ITEMS * PKT_BLOCK;
 constexpr int RS_WAVES = PKT_BLOCK / PKT_WAVE;
 static_assert(PKT_BLOCK == RS_BINS, "one thread per digit");
@@ -42,45 +43,79 @@ inline int bit_width(i64 x) {
   return b;
 }
 
-// One radix pass over tile blockIdx.x: without SCATTER the tile's digit counts go
-// to hist[digit * tiles + tile]; with it every pair goes to start[digit * tiles +
-// tile] + its stable rank among the tile's pairs of that digit.
-template <bool SCATTER>
-__global__ __launch_bounds__(PKT_BLOCK) void k_rs_pass(i64 cnt, i64 tiles, const u32* __restrict__ keys,
-                                                      const i32* __restrict__ vals, int shift, i32* __restrict__ hist,
-                                                      const i64* __restrict__ start, u32* __restrict__ okeys,
-                                                      i32* __restrict__ ovals) {
+// Lanes of this wave whose digit equals this lane's (valid lanes only).
+__device__ __forceinline__ u64 same_digit(bool valid, int d) {
+  u64 same = __ballot(valid);
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const bool bit = (d >> b) & 1;
+    const u64 bb = __ballot(bit);
+    same &= bit ? bb : ~bb;
+  }
+  return same;
+}
+
+// Digit counts of tile blockIdx.x into hist[digit * tiles + tile]: one LDS atomic
+// per run of equal digits in a wave.
+__global__ __launch_bounds__(PKT_BLOCK) void k_rs_count(i64 cnt, i64 tiles, const u32* __restrict__ keys, int shift,
+                                                       i32* __restrict__ hist) {
+  __shared__ i32 h[RS_BINS];
+  const int tid = threadIdx.x, lane = lane_id();
+  const i64 t = blockIdx.x;
+  h[tid] = 0;
+  __syncthreads();
+  const u64 below = (1ull << lane) - 1ull;
+  for (int sub = 0; sub < RS_ITEMS; ++sub) {
+    const i64 i = t * RS_TILE + (i64)sub * PKT_BLOCK + tid;
+    const bool valid = i < cnt;
+    const int d = valid ? (int)((keys[i] >> shift) & (u32)(RS_BINS - 1)) : 0;
+    const u64 same = same_digit(valid, d);
+    if (valid && __popcll(same & below) == 0) atomicAdd(&h[d], __popcll(same));
+  }
+  __syncthreads();
+  hist[(i64)tid * tiles + t] = h[tid];
+}
+
+// Scatter of tile blockIdx.x.  Every pair's stable rank among the tile's pairs of
+// its digit (earlier sub-steps, then lower waves, then lower lanes first) puts it
+// into LDS in digit order; the tile then leaves LDS in that order, so that the
+// lanes of a wave write runs of consecutive places: pair p of digit d goes to
+// start[d * tiles + tile] + (p - first LDS place of d).
+__global__ __launch_bounds__(PKT_BLOCK) void k_rs_scatter(i64 cnt, i64 tiles, const u32* __restrict__ keys,
+                                                         const i32* __restrict__ vals, int shift,
+                                                         const i32* __restrict__ hist, const i64* __restrict__ start,
+                                                         u32* __restrict__ okeys, i32* __restrict__ ovals) {
+  __shared__ u32 lk[RS_TILE];
+  __shared__ i32 lv[RS_TILE];
   __shared__ i32 wc[RS_WAVES][RS_BINS];  // this sub-step's count per wave and digit
-  __shared__ i32 run[RS_BINS];           // the tile's count per digit before this sub-step
+  __shared__ i32 run[RS_BINS];           // the tile's pairs per digit before this sub-step
+  __shared__ i32 lstart[RS_BINS];        // first LDS place of every digit
   __shared__ i64 base[RS_BINS];
+  __shared__ i64 tmp[RS_WAVES];
   const int tid = threadIdx.x, wid = tid / PKT_WAVE, lane = lane_id();
   const i64 t = blockIdx.x;
+  i64 total;
+  lstart[tid] = (i32)block_excl_scan_i64((i64)hist[(i64)tid * tiles + t], tmp, &total);
+  base[tid] = start[(i64)tid * tiles + t];
   run[tid] = 0;
   for (int w = 0; w < RS_WAVES; ++w) wc[w][tid] = 0;
-  if (SCATTER) base[tid] = start[(i64)tid * tiles + t];
   __syncthreads();
   const u64 below = (1ull << lane) - 1ull;
   for (int sub = 0; sub < RS_ITEMS; ++sub) {
     const i64 i = t * RS_TILE + (i64)sub * PKT_BLOCK + tid;
     const bool valid = i < cnt;
     const u32 key = valid ? keys[i] : 0u;
+    const i32 val = valid ? vals[i] : 0;
     const int d = (int)((key >> shift) & (u32)(RS_BINS - 1));
-    u64 same = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const bool bit = (d >> b) & 1;
-      const u64 bb = __ballot(bit);
-      same &= bit ? bb : ~bb;
-    }
+    const u64 same = same_digit(valid, d);
     const int lower = __popcll(same & below);
     if (valid && lower == 0) wc[wid][d] = __popcll(same);
     __syncthreads();
-    if (SCATTER && valid) {
-      i32 r = run[d] + lower;
+    if (valid) {
+      i32 r = lstart[d] + run[d] + lower;
       for (int w = 0; w < wid; ++w) r += wc[w][d];
-      const i64 pos = base[d] + r;
-      okeys[pos] = key;
-      ovals[pos] = vals[i];
+      lk[r] = key;
+      lv[r] = val;
     }
     __syncthreads();
     i32 tot = 0;
@@ -91,7 +126,13 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_rs_pass(i64 cnt, i64 tiles, const
     run[tid] += tot;
     __syncthreads();
   }
-  if (!SCATTER) hist[(i64)tid * tiles + t] = run[tid];
+  for (i64 p = tid; p < total; p += PKT_BLOCK) {
+    const u32 key = lk[p];
+    const int d = (int)((key >> shift) & (u32)(RS_BINS - 1));
+    const i64 pos = base[d] + (p - lstart[d]);
+    okeys[pos] = key;
+    ovals[pos] = lv[p];
+  }
 }
 
 struct HistLen {
@@ -132,13 +173,11 @@ truss_status rs_sort(i64 cnt, int bits, const RsBufs& b, hipStream_t s, int* sel
       return TRUSS_E_ARG;
     }
     for (int shift = 0; shift < bits; shift += 8) {
-      hipLaunchKernelGGL(k_rs_pass<false>, dim3((unsigned)tiles), dim3(PKT_BLOCK), 0, s, cnt, tiles,
-                         (const u32*)b.k[q], (const i32*)b.v[q], shift, b.hist, (const i64*)nullptr,
-                         (u32*)nullptr, (i32*)nullptr);
+      hipLaunchKernelGGL(k_rs_count, dim3((unsigned)tiles), dim3(PKT_BLOCK), 0, s, cnt, tiles, (const u32*)b.k[q],
+                         shift, b.hist);
       PKT_HIP(scan_launch(HistLen{b.hist, tiles * RS_BINS}, b.partial, b.start, b.arrive, s));
-      hipLaunchKernelGGL(k_rs_pass<true>, dim3((unsigned)tiles), dim3(PKT_BLOCK), 0, s, cnt, tiles,
-                         (const u32*)b.k[q], (const i32*)b.v[q], shift, (i32*)nullptr, (const i64*)b.start,
-                         b.k[q ^ 1], b.v[q ^ 1]);
+      hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)tiles), dim3(PKT_BLOCK), 0, s, cnt, tiles, (const u32*)b.k[q],
+                         (const i32*)b.v[q], shift, (const i32*)b.hist, (const i64*)b.start, b.k[q ^ 1], b.v[q ^ 1]);
       PKT_LAUNCH_CHECK();
       q ^= 1;
     }
@@ -173,8 +212,14 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_ko_init(i32 n, const i32* __restr
       mx = max(mx, c);
     }
   }
+  __shared__ i32 wm[RS_WAVES];
   mx = wave_max_i32(mx);
-  if (lane_id() == 0 && mx > 0) atomicMax(&fl->kmax, mx);
+  if (lane_id() == 0) wm[threadIdx.x / PKT_WAVE] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {  // one atomic per block: per-wave ones on one address serialise
+    for (int w = 1; w < RS_WAVES; ++w) mx = max(mx, wm[w]);
+    if (mx > 0) atomicMax(&fl->kmax, mx);
+  }
 }
 
 __global__ __launch_bounds__(PKT_BLOCK) void k_ko_out(i32 n, const i32* __restrict__ sorted, i32* __restrict__ order,
@@ -229,22 +274,35 @@ struct RelabelRows {
 };
 
 // Slot j of old row u becomes the pair (new_id[adj[j]], new_id[u]) at place
-// off2[new_id[u]] + (j - off[u]): grouped by the new id of u, increasing.
+// off2[new_id[u]] + (j - off[u]): grouped by the new id of u, increasing.  A block
+// takes PKT_BLOCK consecutive slots at a time and finds the rows of its first and
+// last slot once, so every lane searches only the few rows in between.
 __global__ __launch_bounds__(PKT_BLOCK) void k_rl_pairs(i32 n, i64 two_m, const i64* __restrict__ off,
                                                        const i32* __restrict__ adj, const i32* __restrict__ new_id,
                                                        const i64* __restrict__ off2, u32* __restrict__ keys,
                                                        i32* __restrict__ vals, KoFlags* fl) {
-  for (i64 j = (i64)blockIdx.x * PKT_BLOCK + threadIdx.x; j < two_m; j += (i64)gridDim.x * PKT_BLOCK) {
-    const i32 u = (i32)(upper_bound_dev(off, (i64)0, (i64)n + 1, j) - 1);
-    const i32 w = adj[j];
-    if (w < 0 || w >= n) {  // checked before any use as an index
-      atomicOr(&fl->err, 4u);
-      continue;
+  __shared__ i64 rows[2];
+  const i64 chunks = (two_m + PKT_BLOCK - 1) / PKT_BLOCK;
+  for (i64 c = blockIdx.x; c < chunks; c += gridDim.x) {  // uniform over the block
+    const i64 j0 = c * PKT_BLOCK;
+    const i64 j1 = min(j0 + PKT_BLOCK, two_m) - 1;
+    if (threadIdx.x < 2)
+      rows[threadIdx.x] = upper_bound_dev(off, (i64)0, (i64)n + 1, threadIdx.x == 0 ? j0 : j1) - 1;
+    __syncthreads();
+    const i64 j = j0 + threadIdx.x;
+    if (j <= j1) {
+      const i32 u = (i32)(upper_bound_dev(off, rows[0], rows[1] + 1, j) - 1);
+      const i32 w = adj[j];
+      if (w < 0 || w >= n) {  // checked before any use as an index
+        atomicOr(&fl->err, 4u);
+      } else {
+        const i32 y = new_id[u];
+        const i64 pos = off2[y] + (j - off[u]);
+        keys[pos] = (u32)new_id[w];
+        vals[pos] = y;
+      }
     }
-    const i32 y = new_id[u];
-    const i64 pos = off2[y] + (j - off[u]);
-    keys[pos] = (u32)new_id[w];
-    vals[pos] = y;
+    __syncthreads();  // rows[] is rewritten for the next chunk
   }
 }
 
@@ -277,14 +335,21 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_map_check(i32 n, i64 two_m, const
   }
 }
 
-// Canonical edges of row x of the relabelled graph: its entries above x.
+// First entry of row x of the relabelled graph above x: its canonical edges run
+// from there to the row's end.
+__global__ __launch_bounds__(PKT_BLOCK) void k_first_upper(i32 n, const i64* __restrict__ off2,
+                                                          const i32* __restrict__ adj2, i64* __restrict__ fa) {
+  for (i64 x = (i64)blockIdx.x * PKT_BLOCK + threadIdx.x; x < n; x += (i64)gridDim.x * PKT_BLOCK)
+    fa[x] = upper_bound_dev(adj2, off2[x], off2[x + 1], (i32)x);
+}
+
 struct UpperRows {
   const i64* off2;
-  const i32* adj2;
+  const i64* fa;
   i32 n;
   __device__ bool active() const { return true; }
   __device__ i64 count() const { return n; }
-  __device__ i64 len(i64 x) const { return off2[x + 1] - upper_bound_dev(adj2, off2[x], off2[x + 1], (i32)x); }
+  __device__ i64 len(i64 x) const { return off2[x + 1] - fa[x]; }
 };
 
 // tau[e] = tau2[edge id of (new_id[u], new_id[v]) in the relabelled graph]: the
@@ -293,8 +358,8 @@ struct UpperRows {
 __global__ __launch_bounds__(PKT_BLOCK) void k_map(i32 n, i64 m, const i32* __restrict__ eu,
                                                   const i32* __restrict__ ev, const i32* __restrict__ new_id,
                                                   const i64* __restrict__ off2, const i32* __restrict__ adj2,
-                                                  const i64* __restrict__ U, const i32* __restrict__ tau2,
-                                                  i32* __restrict__ tau, KoFlags* fl) {
+                                                  const i64* __restrict__ FA, const i64* __restrict__ U,
+                                                  const i32* __restrict__ tau2, i32* __restrict__ tau, KoFlags* fl) {
   for (i64 e = (i64)blockIdx.x * PKT_BLOCK + threadIdx.x; e < m; e += (i64)gridDim.x * PKT_BLOCK) {
     const i32 u = eu[e], v = ev[e];
     i32 t = -1;
@@ -304,7 +369,7 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_map(i32 n, i64 m, const i32* __re
       const i32 x = new_id[u], y = new_id[v];
       const i32 a = min(x, y), b = max(x, y);
       const i64 end = off2[a + 1];
-      const i64 fa = upper_bound_dev(adj2, off2[a], end, a);
+      const i64 fa = FA[a];
       const i64 pos = lower_bound_dev(adj2, fa, end, b);
       const i64 id = U[a] + (pos - fa);
       if (a == b || pos == end || adj2[pos] != b || id >= m)
@@ -316,12 +381,14 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_map(i32 n, i64 m, const i32* __re
   }
 }
 
-size_t map_layout(i32 n, void* ws, i64** U, i64** partial, u32** arrive, KoFlags** fl) {
+size_t map_layout(i32 n, void* ws, i64** FA, i64** U, i64** partial, u32** arrive, KoFlags** fl) {
   Carver cv(ws);
+  i64* f0 = cv.take<i64>((size_t)n);
   i64* u = cv.take<i64>((size_t)n + 1);
   i64* p = cv.take<i64>(SCAN_BLOCKS + 1);
   u32* a = cv.take<u32>(1);
   KoFlags* f = cv.take<KoFlags>(1);
+  if (FA) *FA = f0;
   if (U) *U = u;
   if (partial) *partial = p;
   if (arrive) *arrive = a;
@@ -466,7 +533,7 @@ extern "C" truss_status truss_kco_map_workspace_bytes(int32_t n, size_t* bytes) 
     pkt::set_error("bad arguments to truss_kco_map_workspace_bytes");
     return TRUSS_E_ARG;
   }
-  *bytes = map_layout(n, nullptr, nullptr, nullptr, nullptr, nullptr);
+  *bytes = map_layout(n, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
   return TRUSS_OK;
 }
 
@@ -482,7 +549,7 @@ extern "C" truss_status truss_kco_map(int32_t n, int64_t m, const int32_t* el_u,
     set_error("bad n, m or a NULL argument");
     return TRUSS_E_ARG;
   }
-  if (!ws_ok(workspace, workspace_bytes, map_layout(n, nullptr, nullptr, nullptr, nullptr, nullptr)))
+  if (!ws_ok(workspace, workspace_bytes, map_layout(n, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr)))
     return TRUSS_E_WORKSPACE;
   if (m == 0) return TRUSS_OK;
   hipStream_t s = (hipStream_t)stream;
@@ -493,10 +560,10 @@ extern "C" truss_status truss_kco_map(int32_t n, int64_t m, const int32_t* el_u,
     set_error("offsets2[n] = %lld, not 2m = %lld", (long long)two_m, (long long)(2 * m));
     return TRUSS_E_ARG;
   }
-  i64 *U, *partial;
+  i64 *FA, *U, *partial;
   u32* arrive;
   KoFlags* fl;
-  map_layout(n, workspace, &U, &partial, &arrive, &fl);
+  map_layout(n, workspace, &FA, &U, &partial, &arrive, &fl);
   PKT_HIP(hipMemsetAsync(fl, 0, sizeof(KoFlags), s));
   PKT_HIP(hipMemsetAsync(arrive, 0, sizeof(u32), s));
   hipLaunchKernelGGL(k_map_check, dim3(ko_grid(n)), dim3(PKT_BLOCK), 0, s, n, two_m, offsets2, new_id, fl);
@@ -508,9 +575,10 @@ extern "C" truss_status truss_kco_map(int32_t n, int64_t m, const int32_t* el_u,
                          : "new_id: a value outside [0, n)");
     return TRUSS_E_RANGE;
   }
-  PKT_HIP((scan_launch<UpperRows, true>(UpperRows{offsets2, adj2, n}, partial, U, arrive, s)));
+  hipLaunchKernelGGL(k_first_upper, dim3(ko_grid(n)), dim3(PKT_BLOCK), 0, s, n, offsets2, adj2, FA);
+  PKT_HIP(scan_launch(UpperRows{offsets2, FA, n}, partial, U, arrive, s));
   hipLaunchKernelGGL(k_map, dim3(ko_grid(m)), dim3(PKT_BLOCK), 0, s, n, (i64)m, el_u, el_v, new_id, offsets2, adj2,
-                     (const i64*)U, trussness2, trussness, fl);
+                     (const i64*)FA, (const i64*)U, trussness2, trussness, fl);
   PKT_LAUNCH_CHECK();
   if (truss_status st = read_flags(fl, &h, s)) return st;
   if (h.err) {
