@@ -119,19 +119,26 @@ def triangles_by_edge_ids(edges):
     return np.array(tris, dtype=np.int64).reshape(-1, 3)
 
 
-def hindex_truss(edges, max_iter=10_000):
-    """Trussness by the local h-index iteration, as an array in canonical edge order."""
+def hindex_estimates(edges, sweeps=None):
+    """Estimates of the local h-index iteration after `sweeps` sweeps (None: until none
+    changes), in canonical edge order, and the number of sweeps that changed an edge.
+
+    Sweep 0 is the support; every sweep gives each edge, all at once, the h-index of
+    min(estimate(f1), estimate(f2)) over its triangles {e, f1, f2} under the previous
+    sweep's estimates.  The fixed point is trussness - 2.
+    """
     E = canonical_edges(edges)
     m = len(E)
     T = triangles_by_edge_ids(E)
     est = np.bincount(T.ravel(), minlength=m).astype(np.int64) if len(T) else np.zeros(m, np.int64)
     if len(T) == 0:
-        return est + 2
+        return est, 0
     # every triangle gives each of its edges the value min(est of the other two)
     owner = np.concatenate([T[:, 0], T[:, 1], T[:, 2]])
     o1 = np.concatenate([T[:, 1], T[:, 0], T[:, 0]])
     o2 = np.concatenate([T[:, 2], T[:, 2], T[:, 1]])
-    for _ in range(max_iter):
+    done = 0
+    while sweeps is None or done < sweeps:
         val = np.minimum(est[o1], est[o2])
         order = np.lexsort((-val, owner))  # by owner, then value descending
         ow, vv = owner[order], val[order]
@@ -141,6 +148,15 @@ def hindex_truss(edges, max_iter=10_000):
         h = np.zeros(m, np.int64)
         h[ow[starts]] = np.maximum.reduceat(cand, starts)
         if np.array_equal(h, est):
-            return est + 2
+            break
         est = h
-    raise RuntimeError("h-index iteration did not converge")
+        done += 1
+        if done > 10_000:
+            raise RuntimeError("h-index iteration did not converge")
+    return est, done
+
+
+def hindex_truss(edges, max_iter=10_000):
+    """Trussness by the local h-index iteration, as an array in canonical edge order."""
+    est, _ = hindex_estimates(edges)
+    return est + 2
