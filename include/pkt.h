@@ -312,6 +312,33 @@ truss_status truss_kco_map(int32_t n, int64_t m, const int32_t* el_u, const int3
                            const int64_t* offsets2, const int32_t* adj2, const int32_t* trussness2,
                            int32_t* trussness, void* workspace, size_t workspace_bytes, void* stream);
 
+/* Trussness by the local h-index iteration, the barrier-free alternative to the
+ * level-synchronous loop that the related-work section cites (Sariyuce et al.'s
+ * local nucleus decomposition): sweep 0 sets every edge's estimate to its support,
+ * and every sweep gives each edge, all at once, the h-index of
+ * min(estimate(f1), estimate(f2)) over its triangles {e, f1, f2} under the
+ * previous sweep's estimates; the estimates stop at trussness - 2.
+ *   n, offsets, adj  device: a simple symmetric CSR with rows strictly increasing
+ *                    (int64[n+1] starting at 0, int32[2m]), 2m < 2^31
+ *   trussness        device, int32[m] out, canonical edge order (as truss_decompose):
+ *                    estimate + 2 after the last sweep run
+ *   max_sweeps       sweeps to run at most after sweep 0; < 0: until none changes
+ *   sweeps           host, may be NULL: sweeps run that changed an estimate
+ *   converged        host, may be NULL: 1 if a sweep changed nothing (the output is
+ *                    then the trussness), else 0
+ *   workspace        device, truss_hindex_workspace_bytes(n, 2m) bytes (about 9
+ *                    bytes per adjacency slot and 16 per vertex), 256-byte aligned
+ * Work per sweep is the triangle walk of every edge whose neighbourhood changed,
+ * one to three times; the host synchronises once per sweep.  Errors: TRUSS_E_ARG,
+ * TRUSS_E_RANGE (offsets, a neighbour outside [0, n), an unsorted row, a CSR that is
+ * not symmetric or has a self loop), TRUSS_E_WORKSPACE, TRUSS_E_DEVICE,
+ * TRUSS_E_INTERNAL.
+ */
+truss_status truss_hindex_workspace_bytes(int32_t n, int64_t two_m, size_t* bytes);
+truss_status truss_hindex(int32_t n, const int64_t* offsets, const int32_t* adj, int32_t* trussness,
+                          int32_t max_sweeps, int32_t* sweeps, int32_t* converged, void* workspace,
+                          size_t workspace_bytes, void* stream);
+
 /*
  * Batched decomposition of many independent graphs.  By default they are
  * decomposed together as one disjoint union (one level loop and one launch

@@ -134,6 +134,9 @@ _SIGS = {
                         + [ctypes.c_void_p]),
     "truss_ktruss_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p]),
     "truss_kcore_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p]),
+    "truss_hindex_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p]),
+    "truss_hindex": (ctypes.c_int, [ctypes.c_int32] + [ctypes.c_void_p] * 3 + [ctypes.c_int32]
+                     + [ctypes.c_void_p] * 3 + [ctypes.c_size_t, ctypes.c_void_p]),
     "truss_kco_order_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p]),
     "truss_kco_order": (ctypes.c_int, [ctypes.c_int32] + [ctypes.c_void_p] * 4 + [ctypes.c_size_t, ctypes.c_void_p]),
     "truss_kco_relabel_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p]),
@@ -401,6 +404,26 @@ def kcore(offsets, adj, *, stream=None):
     _check(lib.truss_kcore(int(n), _ptr(off_t), _ptr(adj_t), _ptr(out), ctypes.byref(cmax), ctypes.c_void_p(wptr),
                            nb.value, _stream(torch, stream)))
     return out[:n], int(cmax.value)
+
+
+def hindex(offsets, adj, *, max_sweeps=-1, stream=None):
+    """Trussness by the local h-index iteration: (int32 [m] CUDA tensor, sweeps that changed
+    an estimate, converged).  With max_sweeps >= 0 the estimates + 2 after that many sweeps."""
+    torch = _torch()
+    lib = load()
+    off_t = _dev(offsets, torch.int64, torch)
+    adj_t = _dev(adj, torch.int32, torch)
+    n = off_t.numel() - 1
+    two_m = adj_t.numel()
+    nb = ctypes.c_size_t(0)
+    _check(lib.truss_hindex_workspace_bytes(int(n), int(two_m), ctypes.byref(nb)))
+    _buf, wptr = alloc_workspace(nb.value)
+    out = torch.empty(max(two_m // 2, 1), dtype=torch.int32, device="cuda")
+    sw = ctypes.c_int32(0)
+    conv = ctypes.c_int32(0)
+    _check(lib.truss_hindex(int(n), _ptr(off_t), _ptr(adj_t), _ptr(out), int(max_sweeps), ctypes.byref(sw),
+                            ctypes.byref(conv), ctypes.c_void_p(wptr), nb.value, _stream(torch, stream)))
+    return out[:two_m // 2], int(sw.value), bool(conv.value)
 
 
 def kco_order(core, *, stream=None):
