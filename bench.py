@@ -88,7 +88,7 @@ def _timed(fn, steps, warmup, torch):
 
 def extras(pkt, torch, gg, off20, adj20, m20, ms20, steps):
     """The other parts of the metric: the level loop's drivers, the k-truss listing, core
-    numbers, KCO reordering, learned dispatch vs the plain heuristic (R-MAT s20 and s24), R-MAT s24 itself,
+    numbers, KCO reordering, the local h-index iteration, learned dispatch vs the plain heuristic (R-MAT s20 and s24), R-MAT s24 itself,
     and batched (one union level loop) vs one graph after another.  Inputs resident, as
     for the main line."""
     from paper_1707_02000_amd import tuner
@@ -134,6 +134,15 @@ def extras(pkt, torch, gg, off20, adj20, m20, ms20, steps):
                          "decompose_relabelled_ms": round(td * 1e3, 3), "map_ms": round(tm * 1e3, 3),
                          "trussness_unchanged": same}
     print(f"bench: kcore + KCO rmat20 {out['kcore_rmat20']['ms']} ms, {out['kco_rmat20']}", file=sys.stderr, flush=True)
+    # the local h-index iteration on the same graph (one run: it takes seconds)
+    t0 = time.perf_counter()
+    tau_h, hs, hc = pkt.hindex(off20, adj20)
+    torch.cuda.synchronize()
+    th = time.perf_counter() - t0
+    out["hindex_rmat20"] = {"ms": round(th * 1e3, 1), "sweeps": hs, "converged": hc,
+                            "same_as_pkt": bool(torch.equal(tau_h, tau20)), "vs_pkt_time": th / (ms20 / 1e3)}
+    print(f"bench: h-index rmat20 {out['hindex_rmat20']}", file=sys.stderr, flush=True)
+    del tau_h
     del core20, nid, order, off2, adj2, tau2, tau20, el20
     print(f"bench: k-core rmat20 {tk * 1e3:.2f} ms, max core {cmax}", file=sys.stderr, flush=True)
     W = tuner.load_weights()
