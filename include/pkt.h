@@ -282,9 +282,10 @@ truss_status truss_kcore(int32_t n, const int64_t* offsets, const int32_t* adj, 
  *   workspace        device, truss_kco_relabel_workspace_bytes(n, 2m) bytes (about
  *                    18 bytes per adjacency slot), 256-byte aligned
  * Errors: TRUSS_E_ARG (NULL buffers, or 2m of 2^35 slots or more), TRUSS_E_RANGE
- * (offsets not starting at 0 or out of order, a neighbour outside [0, n), new_id
- * not a permutation with order its inverse, or a CSR that is not symmetric; the
- * outputs are then undefined), TRUSS_E_WORKSPACE, TRUSS_E_DEVICE.
+ * (offsets not starting at 0 or out of order, a neighbour outside [0, n), or new_id
+ * not a permutation with order its inverse), TRUSS_E_NOT_SYMMETRIC (some (u, v)
+ * without (v, u)); the outputs are then undefined.  TRUSS_E_WORKSPACE,
+ * TRUSS_E_DEVICE.
  *
  * truss_kco_map: trussness per input edge from the trussness of the relabelled graph.
  *   n, m             vertices and edges of the input
@@ -330,9 +331,9 @@ truss_status truss_kco_map(int32_t n, int64_t m, const int32_t* el_u, const int3
  *                    bytes per adjacency slot and 16 per vertex), 256-byte aligned
  * Work per sweep is the triangle walk of every edge whose neighbourhood changed,
  * one to three times; the host synchronises once per sweep.  Errors: TRUSS_E_ARG,
- * TRUSS_E_RANGE (offsets, a neighbour outside [0, n), an unsorted row, a CSR that is
- * not symmetric or has a self loop), TRUSS_E_WORKSPACE, TRUSS_E_DEVICE,
- * TRUSS_E_INTERNAL.
+ * TRUSS_E_RANGE (offsets out of order, a neighbour outside [0, n)),
+ * TRUSS_E_NOT_SIMPLE (a row not strictly increasing, a self loop),
+ * TRUSS_E_NOT_SYMMETRIC, TRUSS_E_WORKSPACE, TRUSS_E_DEVICE, TRUSS_E_INTERNAL.
  */
 truss_status truss_hindex_workspace_bytes(int32_t n, int64_t two_m, size_t* bytes);
 truss_status truss_hindex(int32_t n, const int64_t* offsets, const int32_t* adj, int32_t* trussness,

@@ -67,8 +67,8 @@ struct UpperLen {
 // Edge id of every slot (canonical: row-major rank of (u, v), u < v) and the
 // endpoints of every edge.  A block takes PKT_BLOCK consecutive slots at a time
 // and finds the rows of its first and last slot once.  Error bits: 4 a neighbour
-// outside [0, n), 8 a slot with no mirror (not symmetric, or a self loop), 16 a
-// row not strictly increasing.
+// outside [0, n), 8 a slot with no mirror (or an edge id out of range, which only
+// an asymmetric CSR gives), 16 a row not strictly increasing, 32 a self loop.
 __global__ __launch_bounds__(PKT_BLOCK) void k_hx_eid(i32 n, i64 two_m, i64 m, const i64* __restrict__ off,
                                                      const i32* __restrict__ adj, const i64* __restrict__ fa,
                                                      const i64* __restrict__ U, i32* __restrict__ eid,
@@ -90,7 +90,9 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_hx_eid(i32 n, i64 two_m, i64 m, c
         atomicOr(&fl->err, 4u);
       } else {
         if (j + 1 < off[u + 1] && adj[j + 1] <= v) atomicOr(&fl->err, 16u);
-        if (v > u) {
+        if (v == u) {
+          atomicOr(&fl->err, 32u);
+        } else if (v > u) {
           e = U[u] + (j - fa[u]);
           if (e >= 0 && e < m) {  // unsorted rows could put it anywhere
             eu[e] = u;
@@ -102,7 +104,7 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_hx_eid(i32 n, i64 two_m, i64 m, c
         } else {
           const i64 end = off[v + 1];
           const i64 pos = lower_bound_dev(adj, off[v], end, u);
-          if (v == u || pos == end || adj[pos] != u) {
+          if (pos == end || adj[pos] != u) {
             atomicOr(&fl->err, 8u);
           } else {
             e = U[v] + (pos - fa[v]);
@@ -312,7 +314,7 @@ extern "C" truss_status truss_hindex(int32_t n, const int64_t* offsets, const in
   }
   if (two_m & 1) {
     set_error("offsets[n] = %lld is odd: the CSR is not symmetric", (long long)two_m);
-    return TRUSS_E_RANGE;
+    return TRUSS_E_NOT_SYMMETRIC;
   }
   const i64 m = two_m / 2;
   HxWork w;
@@ -329,22 +331,24 @@ extern "C" truss_status truss_hindex(int32_t n, const int64_t* offsets, const in
   }
   hipLaunchKernelGGL(k_hx_first_upper, dim3(hx_grid(n)), dim3(PKT_BLOCK), 0, s, n, offsets, adj, w.fa);
   PKT_HIP(scan_launch(UpperLen{offsets, w.fa, n}, w.partial, w.U, w.arrive, s));
-  i64 mu = 0;
-  PKT_HIP(hipMemcpyAsync(&mu, w.U + n, sizeof(i64), hipMemcpyDeviceToHost, s));
-  PKT_HIP(hipStreamSynchronize(s));
-  if (mu != m) {
-    set_error("input CSR: %lld entries above the diagonal, not half of %lld", (long long)mu, (long long)two_m);
-    return TRUSS_E_RANGE;
-  }
   hipLaunchKernelGGL(k_hx_eid, dim3(hx_grid(two_m)), dim3(PKT_BLOCK), 0, s, n, two_m, m, offsets, adj,
                      (const i64*)w.fa, (const i64*)w.U, w.eid, w.eu, w.ev, w.fl);
   PKT_LAUNCH_CHECK();
   if (truss_status st = hx_read(w, &h, s)) return st;
-  if (h.err) {
-    set_error(h.err & 4u    ? "input CSR: a neighbour id outside [0, n)"
-              : h.err & 16u ? "input CSR: a row not strictly increasing"
-                            : "input CSR: not symmetric, or a self loop");
+  i64 mu = 0;  // canonical edges found: m exactly when every slot has its mirror
+  PKT_HIP(hipMemcpyAsync(&mu, w.U + n, sizeof(i64), hipMemcpyDeviceToHost, s));
+  PKT_HIP(hipStreamSynchronize(s));
+  if (h.err & 4u) {
+    set_error("input CSR: a neighbour id outside [0, n)");
     return TRUSS_E_RANGE;
+  }
+  if (h.err & (16u | 32u)) {
+    set_error(h.err & 16u ? "input CSR: a row not strictly increasing" : "input CSR: a self loop");
+    return TRUSS_E_NOT_SIMPLE;
+  }
+  if (h.err || mu != m) {
+    set_error("input CSR: (u, v) present without (v, u)");
+    return TRUSS_E_NOT_SYMMETRIC;
   }
   hipLaunchKernelGGL(k_hx_support, dim3(hx_wave_grid(m)), dim3(PKT_BLOCK), 0, s, m, offsets, adj,
                      (const i32*)w.eu, (const i32*)w.ev, w.est[0]);

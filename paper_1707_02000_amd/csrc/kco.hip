@@ -521,8 +521,8 @@ extern "C" truss_status truss_kco_relabel(int32_t n, const int64_t* offsets, con
   if (two_m > 0) PKT_HIP(hipMemcpyAsync(adj2, b.v[q], sizeof(i32) * (size_t)two_m, hipMemcpyDeviceToDevice, s));
   if (truss_status st = read_flags(fl, &h, s)) return st;
   if (h.err) {
-    set_error("input CSR is not symmetric");
-    return TRUSS_E_RANGE;
+    set_error("input CSR: (u, v) present without (v, u)");
+    return TRUSS_E_NOT_SYMMETRIC;
   }
   return TRUSS_OK;
 }

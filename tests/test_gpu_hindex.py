@@ -72,14 +72,15 @@ def test_edge_cases(gpu_lib):
     tau, sweeps, conv = pkt.hindex(np.zeros(4, np.int64), np.zeros(0, np.int32))  # no edges
     assert tau.numel() == 0 and sweeps == 0 and conv
     cases = [
-        ([0, 2, 3, 4], [2, 1, 0, 0]),  # a row not increasing
-        ([0, 2, 4], [0, 1, 0, 1]),  # self loops
-        ([0, 1, 1, 2], [1, 0]),  # not symmetric
-        ([0, 1, 2], [1, 5]),  # a neighbour out of range
-        ([0, 2, 1, 2], [1, 0]),  # offsets out of order
+        ([0, 2, 3, 4], [2, 1, 0, 0], "TRUSS_E_NOT_SIMPLE"),  # a row not increasing
+        ([0, 2, 4], [0, 1, 0, 1], "TRUSS_E_NOT_SIMPLE"),  # self loops
+        ([0, 1, 1, 2], [1, 0], "TRUSS_E_NOT_SYMMETRIC"),  # (2, 0) without (0, 2)
+        ([0, 1, 2, 3], [1, 0, 0], "TRUSS_E_NOT_SYMMETRIC"),  # odd slot count
+        ([0, 1, 2], [1, 5], "TRUSS_E_RANGE"),  # a neighbour out of range
+        ([0, 2, 1, 2], [1, 0], "TRUSS_E_RANGE"),  # offsets out of order
     ]
-    for off, adj in cases:
+    for off, adj, want in cases:
         with pytest.raises(pkt.TrussError) as ei:
             pkt.hindex(np.array(off, np.int64), np.array(adj, np.int32))
-        assert ei.value.name == "TRUSS_E_RANGE", (off, adj)
+        assert ei.value.name == want, (off, adj)
     torch.cuda.synchronize()
