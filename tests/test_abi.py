@@ -124,3 +124,54 @@ def test_product_code_never_touches_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"^\s*(import|from)\s+oracle\b", text, re.M), f
                 assert "wc_truss" not in text, f
+
+
+def _ws(lib, name, *args):
+    nb = ctypes.c_size_t(0)
+    code = getattr(lib, name)(*args, ctypes.byref(nb))
+    return code, nb.value
+
+
+def test_workspace_sizes_of_the_other_entry_points(lib):
+    # host only: sizes grow with the input, stay 256-byte multiples, and cover the
+    # per-slot and per-vertex arrays each call carves out
+    for name in ("truss_ktruss_workspace_bytes", "truss_kcore_workspace_bytes",
+                 "truss_kco_order_workspace_bytes", "truss_kco_map_workspace_bytes"):
+        c1, a = _ws(lib, name, 1000)
+        c2, b = _ws(lib, name, 100_000)
+        assert c1 == 0 and c2 == 0 and 0 < a < b and a % 256 == 0 and b % 256 == 0, name
+        assert _ws(lib, name, -1)[0] == 1, name
+    c, a = _ws(lib, "truss_kcore_workspace_bytes", 1 << 20)
+    assert a >= 5 * 4 * (1 << 20) + 8 * (1 << 20)  # degrees, two alive lists, two frontiers, prefix
+    for name, per_slot in (("truss_kco_relabel_workspace_bytes", 16), ("truss_hindex_workspace_bytes", 9)):
+        c1, a = _ws(lib, name, 1000, 20_000)
+        c2, b = _ws(lib, name, 1000, 2_000_000)
+        assert c1 == 0 and c2 == 0 and a < b and b >= per_slot * 2_000_000, name
+        assert _ws(lib, name, -1, 10)[0] == 1 and _ws(lib, name, 10, -2)[0] == 1, name
+    assert lib.truss_kco_order_workspace_bytes(10, None) == 1
+
+
+def test_other_entry_points_reject_bad_arguments_before_device_work(lib):
+    # every check here returns before the first HIP call, so it runs without a GPU
+    vp = ctypes.c_void_p
+    assert lib.truss_ktruss(3, -1, None, None, None, 3, None, None, None, 0, None) == 1  # m < 0
+    assert lib.truss_ktruss(3, 1, None, None, None, 1, None, None, None, 0, None) == 1  # k < 2
+    assert lib.truss_ktruss(3, 2, None, None, None, 3, None, None, None, 0, None) == 1  # NULL edges
+    assert lib.truss_kcore(-1, None, None, None, None, None, 0, None) == 1
+    assert lib.truss_kcore(4, None, None, None, None, None, 0, None) == 1  # NULL offsets
+    host = (ctypes.c_int64 * 8)()
+    # a workspace too small or misaligned is refused before the offsets are read
+    assert lib.truss_kcore(4, host, host, host, None, None, 0, None) == 5
+    assert lib.truss_kco_order(-1, None, None, None, None, 0, None) == 1
+    assert lib.truss_kco_order(4, None, host, host, None, 0, None) == 1  # NULL core
+    assert lib.truss_kco_order(4, host, host, host, vp(4096 + 8), 1 << 20, None) == 5  # misaligned
+    assert lib.truss_kco_relabel(-1, None, None, None, None, host, None, None, 0, None) == 1
+    assert lib.truss_kco_relabel(4, host, host, host, host, None, None, None, 0, None) == 1  # NULL offsets2
+    assert lib.truss_kco_map(-1, 0, None, None, None, None, None, None, None, None, 0, None) == 1
+    assert lib.truss_kco_map(0, 3, host, host, None, None, host, host, host, None, 0, None) == 1  # m > 0, n = 0
+    sweeps, conv = ctypes.c_int32(7), ctypes.c_int32(7)
+    assert lib.truss_hindex(-1, None, None, None, -1, ctypes.byref(sweeps), ctypes.byref(conv), None, 0,
+                            None) == 1
+    assert sweeps.value == 0 and conv.value == 0  # outputs cleared first
+    assert lib.truss_hindex(4, None, None, None, -1, None, None, None, 0, None) == 1  # NULL offsets
+    assert lib.truss_last_error()
