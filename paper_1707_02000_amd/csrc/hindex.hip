@@ -379,6 +379,7 @@ extern "C" truss_status truss_hindex(int32_t n, const int64_t* offsets, const in
   }
   hipLaunchKernelGGL(k_hx_out, dim3(hx_grid(m)), dim3(PKT_BLOCK), 0, s, m, (const i32*)w.est[q], trussness);
   PKT_LAUNCH_CHECK();
+  PKT_HIP(hipStreamSynchronize(s));  // the output is complete when the call returns
   if (sweeps) *sweeps = done;
   if (converged) *converged = conv ? 1 : 0;
   return TRUSS_OK;
