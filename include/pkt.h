@@ -281,8 +281,8 @@ truss_status truss_kcore(int32_t n, const int64_t* offsets, const int32_t* adj, 
  *   adj2             device, int32[2m] out (NULL when m = 0)
  *   workspace        device, truss_kco_relabel_workspace_bytes(n, 2m) bytes (about
  *                    18 bytes per adjacency slot), 256-byte aligned
- * Errors: TRUSS_E_ARG (NULL buffers, or 2m of 2^35 slots or more), TRUSS_E_RANGE
- * (offsets not starting at 0 or out of order, a neighbour outside [0, n), or new_id
+ * Errors: TRUSS_E_ARG (NULL buffers), TRUSS_E_RANGE (2m above (2^24 - 1) * 2^11,
+ * offsets not starting at 0 or out of order, a neighbour outside [0, n), or new_id
  * not a permutation with order its inverse), TRUSS_E_NOT_SYMMETRIC (some (u, v)
  * without (v, u)); the outputs are then undefined.  TRUSS_E_WORKSPACE,
  * TRUSS_E_DEVICE.

@@ -477,8 +477,9 @@ extern "C" truss_status truss_kco_relabel(int32_t n, const int64_t* offsets, con
     PKT_HIP(hipMemcpyAsync(&two_m, offsets + n, sizeof(i64), hipMemcpyDeviceToHost, s));
     PKT_HIP(hipStreamSynchronize(s));
   }
-  if (two_m < 0 || two_m > ((i64)1 << 40)) {
-    set_error("offsets[n] = %lld is out of range", (long long)two_m);
+  const i64 max_slots = (((i64)1 << 24) - 1) * RS_TILE;  // the radix sort's launch limit
+  if (two_m < 0 || two_m > max_slots) {
+    set_error("offsets[n] = %lld is out of range [0, %lld]", (long long)two_m, (long long)max_slots);
     return TRUSS_E_RANGE;
   }
   if (two_m > 0 && (adj == nullptr || adj2 == nullptr)) {
