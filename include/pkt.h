@@ -215,7 +215,7 @@ truss_status truss_edge_list(int32_t n, const int64_t* offsets, const int32_t* a
                              int32_t* el_v, void* workspace, size_t workspace_bytes, void* stream);
 
 /*
- * The maximal k-trusses, given the trussness (Background section: a k-truss is
+ * The maximal k-trusses, given the trussness (Introduction and Background: a k-truss is
  * a maximal connected subgraph in which every edge lies in at least k - 2
  * triangles of the subgraph).  The edges of trussness >= k contain every k-truss
  * and have that property themselves, so the k-trusses are their connected
@@ -242,7 +242,7 @@ truss_status truss_ktruss(int32_t n, int64_t m, const int32_t* el_u, const int32
  * Core numbers of every vertex (k-core decomposition: the k-core is the maximal
  * subgraph of minimum degree >= k, and the core number of v the largest k whose
  * k-core holds v), by the level-synchronous vertex peeling that the PKT section
- * carries over to edges (related-work section, parallel k-core decomposition).
+ * carries over to edges (Background section, parallel k-core decomposition).
  *   n, offsets, adj  the CSR contract of truss_decompose (device); isolated
  *                    vertices get core number 0
  *   core             device, int32[n] out
@@ -257,7 +257,7 @@ truss_status truss_kcore_workspace_bytes(int32_t n, size_t* bytes);
 truss_status truss_kcore(int32_t n, const int64_t* offsets, const int32_t* adj, int32_t* core, int32_t* max_core,
                          void* workspace, size_t workspace_bytes, void* stream);
 
-/* Vertex reordering by increasing core number (KCO; Experiments section, the
+/* Vertex reordering by increasing core number (KCO; Performance Results section, the
  * support-computation study and Table 2): relabel the vertices so that ids grow
  * with the core number, decompose the relabelled graph, and map its trussness back
  * (the trussness of an edge does not depend on the labels).  Three calls, all on
@@ -314,7 +314,7 @@ truss_status truss_kco_map(int32_t n, int64_t m, const int32_t* el_u, const int3
                            int32_t* trussness, void* workspace, size_t workspace_bytes, void* stream);
 
 /* Trussness by the local h-index iteration, the barrier-free alternative to the
- * level-synchronous loop that the related-work section cites (Sariyuce et al.'s
+ * level-synchronous loop that the Background section cites (Sariyuce et al.'s
  * local nucleus decomposition): sweep 0 sets every edge's estimate to its support,
  * and every sweep gives each edge, all at once, the h-index of
  * min(estimate(f1), estimate(f2)) over its triangles {e, f1, f2} under the

@@ -12,7 +12,7 @@ the lexicographic order of these pairs (row-major upper triangle of the CSR).
   repeatedly removing edges in fewer than k-2 triangles).
 * ``kcore_numbers``: vertex coreness by repeated removal of a minimum-degree vertex.
 * ``hindex_estimates`` / ``hindex_truss``: the local iteration of Sariyuce et al.
-  that the related-work section cites as an alternative (each edge repeatedly
+  that the Background section cites as an alternative (each edge repeatedly
   takes the h-index of min(tau(f1), tau(f2)) over its triangles {e, f1, f2}, all
   edges at once per sweep); it converges to trussness - 2.  A second, independent
   oracle of the trussness, and the oracle of the GPU's sweeps.

@@ -1,6 +1,6 @@
 """CPU ORACLE (test infrastructure): vertex reordering by increasing core number (KCO).
 
-Experiments section, the study of support computation (Table 2): before support,
+Performance Results section, the study of support computation (Table 2): before support,
 every graph is relabelled so that vertex ids increase with the core number, which
 cuts the oriented triangle-counting work sum_v d+(v)^2 on skewed graphs.  The
 trussness of an edge does not depend on the labels, so the decomposition of the

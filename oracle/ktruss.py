@@ -1,6 +1,6 @@
 """CPU ORACLE (test infrastructure): the maximal k-trusses of a graph, given its trussness.
 
-Background section: a k-truss is a maximal connected subgraph in which every edge
+Introduction and Background sections: a k-truss is a maximal connected subgraph in which every edge
 lies in at least k - 2 triangles of the subgraph.  The edges of trussness >= k form
 the largest subgraph with that triangle property (H_k), and every k-truss lies in
 it, so the k-trusses are exactly the connected components of H_k (two edges of H_k

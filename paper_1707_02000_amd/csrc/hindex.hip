@@ -1,5 +1,5 @@
 // Trussness by the local h-index iteration: the barrier-free alternative to
-// level-synchronous peeling that the related-work section cites (Sariyuce et
+// level-synchronous peeling that the Background section cites (Sariyuce et
 // al.'s nucleus decomposition by repeated local updates, after Montresor et al.'s
 // rule for core numbers).  Sweep 0 sets every edge's estimate to its support;
 // every later sweep gives each edge, all at once, the h-index of

@@ -1,5 +1,5 @@
 // Vertex reordering by increasing core number (KCO) before support, as in the
-// support-computation study of the Experiments section (Table 2): the new ids
+// support-computation study of the Performance Results section (Table 2): the new ids
 // sort vertices by core number (ties by old id), the relabelled CSR keeps every
 // row sorted, and the trussness computed on the relabelled graph is mapped back to
 // the input's edge ids (trussness does not depend on the labels).

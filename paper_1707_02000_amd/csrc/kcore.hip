@@ -1,5 +1,5 @@
 // Core numbers (k-core decomposition) by level-synchronous vertex peeling, the
-// pattern the PKT section borrows for edges (the paper's related-work section on
+// pattern the PKT section borrows for edges (the Background section's passage on
 // parallel k-core decomposition): the core number of v is the largest k such that
 // v lies in the k-core, the maximal subgraph of minimum degree >= k.
 //

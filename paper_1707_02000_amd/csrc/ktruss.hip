@@ -1,4 +1,4 @@
-// Maximal k-trusses from the trussness (Background section of Kabir and
+// Maximal k-trusses from the trussness (Introduction and Background sections of Kabir and
 // Madduri, arXiv:1707.02000: a k-truss is a maximal connected subgraph in which
 // every edge lies in at least k - 2 triangles of the subgraph).  The edges of
 // trussness >= k form the largest subgraph with that property and contain every
