@@ -20,21 +20,12 @@
 #include <limits.h>
 
 #include "common.h"
+#include "launch.h"
 #include "scan.h"
 
 namespace {
 
 constexpr int HX_WAVES = PKT_BLOCK / PKT_WAVE;
-
-inline int hx_grid(i64 count) {
-  const i64 g = (count + PKT_BLOCK - 1) / PKT_BLOCK;
-  return (int)(g < 1 ? 1 : (g > 8192 ? 8192 : g));
-}
-
-inline int hx_wave_grid(i64 items) {  // one wave per item, grid-stride beyond 8192 blocks
-  const i64 g = (items + HX_WAVES - 1) / HX_WAVES;
-  return (int)(g < 1 ? 1 : (g > 8192 ? 8192 : g));
-}
 
 struct HxFlags {
   u32 err;
@@ -321,7 +312,7 @@ extern "C" truss_status truss_hindex(int32_t n, const int64_t* offsets, const in
   hx_layout(n, two_m, workspace, &w);
   PKT_HIP(hipMemsetAsync(w.fl, 0, sizeof(HxFlags), s));
   PKT_HIP(hipMemsetAsync(w.arrive, 0, sizeof(u32), s));
-  hipLaunchKernelGGL(k_hx_check, dim3(hx_grid(n)), dim3(PKT_BLOCK), 0, s, n, two_m, offsets, w.fl);
+  hipLaunchKernelGGL(k_hx_check, dim3(grid_items(n)), dim3(PKT_BLOCK), 0, s, n, two_m, offsets, w.fl);
   PKT_LAUNCH_CHECK();
   HxFlags h;
   if (truss_status st = hx_read(w, &h, s)) return st;
@@ -329,9 +320,9 @@ extern "C" truss_status truss_hindex(int32_t n, const int64_t* offsets, const in
     set_error("input CSR: offsets not starting at 0, out of order or past offsets[n]");
     return TRUSS_E_RANGE;
   }
-  hipLaunchKernelGGL(k_hx_first_upper, dim3(hx_grid(n)), dim3(PKT_BLOCK), 0, s, n, offsets, adj, w.fa);
+  hipLaunchKernelGGL(k_hx_first_upper, dim3(grid_items(n)), dim3(PKT_BLOCK), 0, s, n, offsets, adj, w.fa);
   PKT_HIP(scan_launch(UpperLen{offsets, w.fa, n}, w.partial, w.U, w.arrive, s));
-  hipLaunchKernelGGL(k_hx_eid, dim3(hx_grid(two_m)), dim3(PKT_BLOCK), 0, s, n, two_m, m, offsets, adj,
+  hipLaunchKernelGGL(k_hx_eid, dim3(grid_items(two_m)), dim3(PKT_BLOCK), 0, s, n, two_m, m, offsets, adj,
                      (const i64*)w.fa, (const i64*)w.U, w.eid, w.eu, w.ev, w.fl);
   PKT_LAUNCH_CHECK();
   if (truss_status st = hx_read(w, &h, s)) return st;
@@ -350,9 +341,9 @@ extern "C" truss_status truss_hindex(int32_t n, const int64_t* offsets, const in
     set_error("input CSR: (u, v) present without (v, u)");
     return TRUSS_E_NOT_SYMMETRIC;
   }
-  hipLaunchKernelGGL(k_hx_support, dim3(hx_wave_grid(m)), dim3(PKT_BLOCK), 0, s, m, offsets, adj,
+  hipLaunchKernelGGL(k_hx_support, dim3(grid_waves(m)), dim3(PKT_BLOCK), 0, s, m, offsets, adj,
                      (const i32*)w.eu, (const i32*)w.ev, w.est[0]);
-  hipLaunchKernelGGL(k_hx_fill_u8, dim3(hx_grid(m)), dim3(PKT_BLOCK), 0, s, w.act[0], m, (u8)1);
+  hipLaunchKernelGGL(k_hx_fill_u8, dim3(grid_items(m)), dim3(PKT_BLOCK), 0, s, w.act[0], m, (u8)1);
   PKT_LAUNCH_CHECK();
   int q = 0;
   i32 done = 0;
@@ -363,9 +354,9 @@ extern "C" truss_status truss_hindex(int32_t n, const int64_t* offsets, const in
       set_error("h-index iteration: sweep bound exceeded");
       return TRUSS_E_INTERNAL;
     }
-    hipLaunchKernelGGL(k_hx_fill_u8, dim3(hx_grid(m)), dim3(PKT_BLOCK), 0, s, w.act[q ^ 1], m, (u8)0);
+    hipLaunchKernelGGL(k_hx_fill_u8, dim3(grid_items(m)), dim3(PKT_BLOCK), 0, s, w.act[q ^ 1], m, (u8)0);
     PKT_HIP(hipMemsetAsync(&w.fl->changed, 0, sizeof(i32), s));
-    hipLaunchKernelGGL(k_hx_sweep, dim3(hx_wave_grid(m)), dim3(PKT_BLOCK), 0, s, m, offsets, adj, (const i32*)w.eid,
+    hipLaunchKernelGGL(k_hx_sweep, dim3(grid_waves(m)), dim3(PKT_BLOCK), 0, s, m, offsets, adj, (const i32*)w.eid,
                        (const i32*)w.eu, (const i32*)w.ev, (const i32*)w.est[q], w.est[q ^ 1], (const u8*)w.act[q],
                        w.act[q ^ 1], w.fl);
     PKT_LAUNCH_CHECK();
@@ -377,7 +368,7 @@ extern "C" truss_status truss_hindex(int32_t n, const int64_t* offsets, const in
     q ^= 1;
     ++done;
   }
-  hipLaunchKernelGGL(k_hx_out, dim3(hx_grid(m)), dim3(PKT_BLOCK), 0, s, m, (const i32*)w.est[q], trussness);
+  hipLaunchKernelGGL(k_hx_out, dim3(grid_items(m)), dim3(PKT_BLOCK), 0, s, m, (const i32*)w.est[q], trussness);
   PKT_LAUNCH_CHECK();
   PKT_HIP(hipStreamSynchronize(s));  // the output is complete when the call returns
   if (sweeps) *sweeps = done;

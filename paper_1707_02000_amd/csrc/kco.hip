@@ -17,6 +17,7 @@
 #include <limits.h>
 
 #include "common.h"
+#include "launch.h"
 #include "scan.h"
 
 namespace {
@@ -26,11 +27,6 @@ constexpr int RS_ITEMS = 8;
 constexpr int RS_TILE = RS_ITEMS * PKT_BLOCK;
 constexpr int RS_WAVES = PKT_BLOCK / PKT_WAVE;
 static_assert(PKT_BLOCK == RS_BINS, "one thread per digit");
-
-inline int ko_grid(i64 count) {
-  const i64 g = (count + PKT_BLOCK - 1) / PKT_BLOCK;
-  return (int)(g < 1 ? 1 : (g > 8192 ? 8192 : g));
-}
 
 inline i64 rs_tiles(i64 cnt) { return (cnt + RS_TILE - 1) / RS_TILE; }
 
@@ -432,7 +428,7 @@ extern "C" truss_status truss_kco_order(int32_t n, const int32_t* core, int32_t*
   ko_layout(n, workspace, &b, &fl);
   PKT_HIP(hipMemsetAsync(fl, 0, sizeof(KoFlags), s));
   PKT_HIP(hipMemsetAsync(b.arrive, 0, sizeof(u32), s));
-  hipLaunchKernelGGL(k_ko_init, dim3(ko_grid(n)), dim3(PKT_BLOCK), 0, s, n, core, b.k[0], b.v[0], fl);
+  hipLaunchKernelGGL(k_ko_init, dim3(grid_items(n)), dim3(PKT_BLOCK), 0, s, n, core, b.k[0], b.v[0], fl);
   PKT_LAUNCH_CHECK();
   KoFlags h;
   if (truss_status st = read_flags(fl, &h, s)) return st;
@@ -442,7 +438,7 @@ extern "C" truss_status truss_kco_order(int32_t n, const int32_t* core, int32_t*
   }
   int q = 0;
   if (truss_status st = rs_sort(n, bit_width(h.kmax), b, s, &q)) return st;
-  hipLaunchKernelGGL(k_ko_out, dim3(ko_grid(n)), dim3(PKT_BLOCK), 0, s, n, (const i32*)b.v[q], order, new_id, fl);
+  hipLaunchKernelGGL(k_ko_out, dim3(grid_items(n)), dim3(PKT_BLOCK), 0, s, n, (const i32*)b.v[q], order, new_id, fl);
   PKT_LAUNCH_CHECK();
   if (truss_status st = read_flags(fl, &h, s)) return st;
   if (h.err) {
@@ -496,7 +492,7 @@ extern "C" truss_status truss_kco_relabel(int32_t n, const int64_t* offsets, con
   rl_layout(two_m, workspace, &b, &fl);
   PKT_HIP(hipMemsetAsync(fl, 0, sizeof(KoFlags), s));
   PKT_HIP(hipMemsetAsync(b.arrive, 0, sizeof(u32), s));
-  hipLaunchKernelGGL(k_rl_check, dim3(ko_grid(n)), dim3(PKT_BLOCK), 0, s, n, two_m, offsets, new_id, order, fl);
+  hipLaunchKernelGGL(k_rl_check, dim3(grid_items(n)), dim3(PKT_BLOCK), 0, s, n, two_m, offsets, new_id, order, fl);
   PKT_LAUNCH_CHECK();
   KoFlags h;
   if (truss_status st = read_flags(fl, &h, s)) return st;
@@ -506,7 +502,7 @@ extern "C" truss_status truss_kco_relabel(int32_t n, const int64_t* offsets, con
     return TRUSS_E_RANGE;
   }
   PKT_HIP(scan_launch(RelabelRows{order, offsets, n}, b.partial, offsets2, b.arrive, s));
-  hipLaunchKernelGGL(k_rl_pairs, dim3(ko_grid(two_m)), dim3(PKT_BLOCK), 0, s, n, two_m, offsets, adj, new_id,
+  hipLaunchKernelGGL(k_rl_pairs, dim3(grid_items(two_m)), dim3(PKT_BLOCK), 0, s, n, two_m, offsets, adj, new_id,
                      (const i64*)offsets2, b.k[0], b.v[0], fl);
   PKT_LAUNCH_CHECK();
   if (truss_status st = read_flags(fl, &h, s)) return st;
@@ -516,7 +512,7 @@ extern "C" truss_status truss_kco_relabel(int32_t n, const int64_t* offsets, con
   }
   int q = 0;
   if (truss_status st = rs_sort(two_m, bit_width((i64)n - 1), b, s, &q)) return st;
-  hipLaunchKernelGGL(k_rl_rows, dim3(ko_grid(n)), dim3(PKT_BLOCK), 0, s, n, two_m, (const u32*)b.k[q],
+  hipLaunchKernelGGL(k_rl_rows, dim3(grid_items(n)), dim3(PKT_BLOCK), 0, s, n, two_m, (const u32*)b.k[q],
                      (const i64*)offsets2, fl);
   PKT_LAUNCH_CHECK();
   if (two_m > 0) PKT_HIP(hipMemcpyAsync(adj2, b.v[q], sizeof(i32) * (size_t)two_m, hipMemcpyDeviceToDevice, s));
@@ -567,7 +563,7 @@ extern "C" truss_status truss_kco_map(int32_t n, int64_t m, const int32_t* el_u,
   map_layout(n, workspace, &FA, &U, &partial, &arrive, &fl);
   PKT_HIP(hipMemsetAsync(fl, 0, sizeof(KoFlags), s));
   PKT_HIP(hipMemsetAsync(arrive, 0, sizeof(u32), s));
-  hipLaunchKernelGGL(k_map_check, dim3(ko_grid(n)), dim3(PKT_BLOCK), 0, s, n, two_m, offsets2, new_id, fl);
+  hipLaunchKernelGGL(k_map_check, dim3(grid_items(n)), dim3(PKT_BLOCK), 0, s, n, two_m, offsets2, new_id, fl);
   PKT_LAUNCH_CHECK();
   KoFlags h;
   if (truss_status st = read_flags(fl, &h, s)) return st;
@@ -576,9 +572,9 @@ extern "C" truss_status truss_kco_map(int32_t n, int64_t m, const int32_t* el_u,
                          : "new_id: a value outside [0, n)");
     return TRUSS_E_RANGE;
   }
-  hipLaunchKernelGGL(k_first_upper, dim3(ko_grid(n)), dim3(PKT_BLOCK), 0, s, n, offsets2, adj2, FA);
+  hipLaunchKernelGGL(k_first_upper, dim3(grid_items(n)), dim3(PKT_BLOCK), 0, s, n, offsets2, adj2, FA);
   PKT_HIP(scan_launch(UpperRows{offsets2, FA, n}, partial, U, arrive, s));
-  hipLaunchKernelGGL(k_map, dim3(ko_grid(m)), dim3(PKT_BLOCK), 0, s, n, (i64)m, el_u, el_v, new_id, offsets2, adj2,
+  hipLaunchKernelGGL(k_map, dim3(grid_items(m)), dim3(PKT_BLOCK), 0, s, n, (i64)m, el_u, el_v, new_id, offsets2, adj2,
                      (const i64*)FA, (const i64*)U, trussness2, trussness, fl);
   PKT_LAUNCH_CHECK();
   if (truss_status st = read_flags(fl, &h, s)) return st;

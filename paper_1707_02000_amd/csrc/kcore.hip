@@ -16,14 +16,10 @@
 #include <limits.h>
 
 #include "common.h"
+#include "launch.h"
 #include "scan.h"
 
 namespace {
-
-inline int kc_grid(i64 count) {
-  const i64 g = (count + PKT_BLOCK - 1) / PKT_BLOCK;
-  return (int)(g < 1 ? 1 : (g > 8192 ? 8192 : g));
-}
 
 struct KcCounters {
   i32 nfound, nkeep, minabove;
@@ -199,7 +195,7 @@ inline int kc_round_grid(i32 nf, i32 k, i64 two_m, i32 n) {
   const i64 avg = (two_m + n - 1) / n;
   i64 est = (i64)nf * (k > avg ? (i64)k : avg);
   if (est > two_m) est = two_m;
-  return kc_grid(est);
+  return grid_items(est);
 }
 
 }  // namespace
@@ -240,7 +236,7 @@ extern "C" truss_status truss_kcore(int32_t n, const int64_t* offsets, const int
   KcWork w;
   kc_layout(n, workspace, &w);
   PKT_HIP(hipMemsetAsync(w.cnt, 0, sizeof(KcCounters), s));
-  hipLaunchKernelGGL(k_kc_init, dim3(kc_grid(n)), dim3(PKT_BLOCK), 0, s, n, two_m, offsets, w.deg, core, w.A[0],
+  hipLaunchKernelGGL(k_kc_init, dim3(grid_items(n)), dim3(PKT_BLOCK), 0, s, n, two_m, offsets, w.deg, core, w.A[0],
                      w.cnt);
   PKT_LAUNCH_CHECK();
   KcCounters hc;

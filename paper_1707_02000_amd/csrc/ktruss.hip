@@ -13,13 +13,9 @@
 #include <limits.h>
 
 #include "common.h"
+#include "launch.h"
 
 namespace {
-
-inline int kt_grid(i64 count) {
-  const i64 g = (count + PKT_BLOCK - 1) / PKT_BLOCK;
-  return (int)(g < 1 ? 1 : (g > 8192 ? 8192 : g));
-}
 
 __device__ __forceinline__ i32 ld_par(const i32* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -182,14 +178,14 @@ extern "C" truss_status truss_ktruss(int32_t n, int64_t m, const int32_t* el_u, 
   PKT_HIP(hipMemsetAsync(w.err, 0, sizeof(u32), s));
   PKT_HIP(hipMemsetAsync(w.count, 0, sizeof(i32), s));
   if (n > 0)
-    hipLaunchKernelGGL(k_kt_init, dim3(kt_grid(n)), dim3(PKT_BLOCK), 0, s, n, w.par, w.first);
+    hipLaunchKernelGGL(k_kt_init, dim3(grid_items(n)), dim3(PKT_BLOCK), 0, s, n, w.par, w.first);
   if (m > 0) {
-    hipLaunchKernelGGL(k_kt_union, dim3(kt_grid(m)), dim3(PKT_BLOCK), 0, s, n, (i64)m, el_u, el_v, trussness, k,
+    hipLaunchKernelGGL(k_kt_union, dim3(grid_items(m)), dim3(PKT_BLOCK), 0, s, n, (i64)m, el_u, el_v, trussness, k,
                        w.par, w.err);
-    if (n > 0) hipLaunchKernelGGL(k_kt_compress, dim3(kt_grid(n)), dim3(PKT_BLOCK), 0, s, n, w.par);
-    hipLaunchKernelGGL(k_kt_first, dim3(kt_grid(m)), dim3(PKT_BLOCK), 0, s, (i64)m, el_u, trussness, k,
+    if (n > 0) hipLaunchKernelGGL(k_kt_compress, dim3(grid_items(n)), dim3(PKT_BLOCK), 0, s, n, w.par);
+    hipLaunchKernelGGL(k_kt_first, dim3(grid_items(m)), dim3(PKT_BLOCK), 0, s, (i64)m, el_u, trussness, k,
                        (const i32*)w.par, w.first, (const u32*)w.err);
-    hipLaunchKernelGGL(k_kt_label, dim3(kt_grid(m)), dim3(PKT_BLOCK), 0, s, (i64)m, el_u, trussness, k,
+    hipLaunchKernelGGL(k_kt_label, dim3(grid_items(m)), dim3(PKT_BLOCK), 0, s, (i64)m, el_u, trussness, k,
                        (const i32*)w.par, (const i32*)w.first, label, w.count, (const u32*)w.err);
   }
   PKT_LAUNCH_CHECK();
