@@ -215,9 +215,9 @@ truss_status truss_edge_list(int32_t n, const int64_t* offsets, const int32_t* a
                              int32_t* el_v, void* workspace, size_t workspace_bytes, void* stream);
 
 /*
- * The maximal k-trusses, given the trussness (Introduction and Background: a k-truss is
- * a maximal connected subgraph in which every edge lies in at least k - 2
- * triangles of the subgraph).  The edges of trussness >= k contain every k-truss
+ * The maximal k-trusses, given the trussness (Introduction and Background
+ * sections: a k-truss is a maximal connected subgraph in which every edge lies in
+ * at least k - 2 triangles of the subgraph).  The edges of trussness >= k contain every k-truss
  * and have that property themselves, so the k-trusses are their connected
  * components (two such edges that share a vertex belong to the same k-truss).
  *   n, m             vertices and edges of the graph (n >= 0, 0 <= m < 2^31)
@@ -249,9 +249,10 @@ truss_status truss_ktruss(int32_t n, int64_t m, const int32_t* el_u, const int32
  *   max_core         host, may be NULL: the largest core number
  * The caller owns every buffer.  Workspace: truss_kcore_workspace_bytes(n)
  * bytes at 256-byte alignment.  The host copies the counters back once per
- * round and once per level (one stream synchronisation each).  Errors: TRUSS_E_ARG, TRUSS_E_RANGE (offsets out
- * of order or past offsets[n], or a neighbour id outside [0, n); core is then
- * undefined), TRUSS_E_WORKSPACE, TRUSS_E_DEVICE, TRUSS_E_INTERNAL.
+ * round and once per level (one stream synchronisation each).  Errors:
+ * TRUSS_E_ARG, TRUSS_E_RANGE (offsets out of order or past offsets[n], or a
+ * neighbour id outside [0, n); core is then undefined), TRUSS_E_WORKSPACE,
+ * TRUSS_E_DEVICE, TRUSS_E_INTERNAL.
  */
 truss_status truss_kcore_workspace_bytes(int32_t n, size_t* bytes);
 truss_status truss_kcore(int32_t n, const int64_t* offsets, const int32_t* adj, int32_t* core, int32_t* max_core,
