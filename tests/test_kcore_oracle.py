@@ -94,3 +94,25 @@ def test_bucket_order_on_a_medium_graph():
     g = gg.workload("rmat12", seed=4)
     edges = [tuple(map(int, p)) for p in oracle.edge_list(g)]
     assert np.array_equal(oracle.kcore(g), D.kcore_numbers(g.n, edges))
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_trussness_within_the_core_numbers(seed):
+    # a k-truss lies in the (k-1)-core: every edge's trussness is at most one more than
+    # the smaller core number of its endpoints (two oracles, one relation)
+    import graphgen as gg
+    import oracle
+
+    rng = random.Random(2000 + seed)
+    n = rng.randint(3, 120)
+    p = rng.uniform(0.02, 0.3)
+    edges = {(u, v) for u in range(n) for v in range(u + 1, n) if rng.random() < p}
+    for _ in range(rng.randint(0, 3)):
+        vs = sorted(rng.sample(range(n), min(n, rng.randint(3, 12))))
+        edges |= set(itertools.combinations(vs, 2))
+    g = gg.from_edges(n, sorted(edges)) if seed else gg.workload("rmat12", seed=3)
+    core = oracle.kcore(g)
+    tau = oracle.truss(g)
+    el = oracle.edge_list(g)
+    if len(el):
+        assert np.all(tau <= np.minimum(core[el[:, 0]], core[el[:, 1]]) + 1)
