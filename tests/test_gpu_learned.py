@@ -66,8 +66,24 @@ def test_gradient_matches_cpu(gpu_lib):
     assert code == 0
     g_ref = ref.gradient(w.astype(np.float64), X.astype(np.float64), T.astype(np.float64), M, K)
     g_gpu = g.cpu().numpy().astype(np.float64)
-    assert np.linalg.norm(g_gpu - g_ref) <= 1e-4 * np.linalg.norm(g_ref) + 1e-7
+    # element by element: fp32 accumulation over 256 rows against fp64
+    tol = 1e-4 * np.abs(g_ref) + 1e-5 * np.abs(g_ref).max()
+    bad = np.flatnonzero(np.abs(g_gpu - g_ref) > tol)
+    assert bad.size == 0, (bad[:10], g_gpu[bad[:10]], g_ref[bad[:10]])
     assert np.isclose(loss.item(), ref.loss(w.astype(np.float64), X, T, M, K), rtol=1e-4)
+
+
+def test_forward_on_hand_built_network(gpu_lib):
+    # the hand-built network of test_mlp_reference.py, whose outputs are known in closed form
+    from paper_1707_02000_amd import tuner
+    import torch
+
+    from test_mlp_reference import hand_network, hand_outputs
+
+    X = np.random.default_rng(9).normal(0, 6, (300, 6)).astype(np.float32)
+    w = hand_network(K).astype(np.float32)
+    Y = tuner.predict(torch.from_numpy(w).cuda(), X)
+    assert np.allclose(Y, hand_outputs(X.astype(np.float64), K), rtol=1e-5, atol=1e-4)
 
 
 def test_choose_matches_cpu_decision(gpu_lib):

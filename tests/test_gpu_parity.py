@@ -214,18 +214,79 @@ def _golden(name):
     return json.load(open(path))
 
 
-@pytest.mark.parametrize("name", ["er4096", "rmat16", "rmat18", "rmat20"])
+@pytest.mark.parametrize("name", ["er4096", "rmat16", "rmat18", "rmat20", "chunglu23", "rmat24"])
 def test_full_size_against_stored_oracle(gpu_lib, name):
+    """Every edge of the full-size workloads, bit for bit, against the stored oracle run."""
+    import torch
+
     rec = _golden(name)
     g = gg.workload(name, seed=rec["seed"])
     assert g.sha256() == rec["csr_sha256"]
     say("case", name, "m", g.m)
-    tau, st = gpu_lib.truss_decompose(g.offsets, g.adj, validate=False, return_stats=True)
+    off, adj = torch.from_numpy(g.offsets).cuda(), torch.from_numpy(g.adj).cuda()
+    tau, st = gpu_lib.truss_decompose(off, adj, validate=False, return_stats=True)
     tau = tau.cpu().numpy()
     assert int(tau.max()) == rec["t_max"]
     assert np.bincount(tau).tolist() == rec["histogram"]
     assert sha(tau) == rec["trussness_sha256"]
     assert st["triangles"] == rec["triangles"]
+    S = gpu_lib.truss_support(off, adj).cpu().numpy()
+    assert sha(S) == rec["support_sha256"]
+
+
+@pytest.mark.parametrize("opts", [
+    dict(device_loop="host"),
+    dict(device_loop="graph"),
+    dict(variant="merge"),
+    dict(force_choice="wide_narrow"),
+    dict(compact=False),
+    dict(owner_rule=1),
+])
+def test_full_size_variants_rmat20(gpu_lib, opts):
+    """Launch variants and loop drivers at the full R-MAT scale-20 size: every one gives
+    the oracle's trussness."""
+    import torch
+
+    rec = _golden("rmat20")
+    g = gg.workload("rmat20", seed=rec["seed"])
+    say("case rmat20", opts)
+    off, adj = torch.from_numpy(g.offsets).cuda(), torch.from_numpy(g.adj).cuda()
+    tau = gpu_lib.truss_decompose(off, adj, validate=False, **opts).cpu().numpy()
+    assert sha(tau) == rec["trussness_sha256"]
+
+
+def _batch_golden(name):
+    path = os.path.join(GOLDEN, f"{name}.txt")
+    if not os.path.exists(path):
+        pytest.skip(f"no stored expectation for {name}")
+    rows = []
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        g, n, m, t, h = line.split()
+        rows.append((int(g), int(n), int(m), int(t), h))
+    return rows
+
+
+@pytest.mark.parametrize("name,mode", [("batch64", "union"), ("batch64", "sequential"), ("batch4096", "union")])
+def test_batch_every_graph_against_stored_oracle(gpu_lib, name, mode):
+    """Every graph of the packed batch workloads against the oracle run on that graph alone."""
+    import torch
+
+    rows = _batch_golden(name)
+    b = gg.workload(name, seed=1)
+    assert b.num_graphs == len(rows)
+    say("case", name, mode, "graphs", b.num_graphs, "total m", b.total_m)
+    dev = [torch.from_numpy(x).cuda() for x in (b.vtx_off, b.adj_off, b.offsets, b.adj)]
+    tau = gpu_lib.truss_decompose_batched(*dev, validate=False, sequential=(mode == "sequential")).cpu().numpy()
+    bad = []
+    for g, n, m, t, h in rows:
+        s = int(b.adj_off[g]) // 2
+        assert int(b.adj_off[g + 1] - b.adj_off[g]) == 2 * m
+        part = tau[s:s + m]
+        if sha(part) != h:
+            bad.append(g)
+    assert not bad, f"{len(bad)} graphs differ, first {bad[:10]}"
 
 
 # ---- peeling-order certificates (oracle/certificate.py): exact at any size
