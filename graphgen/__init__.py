@@ -39,9 +39,12 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB):
-        build()
-    lib = ctypes.CDLL(_LIB)
+    path = os.environ.get("PKT_GRAPHGEN_LIB")  # another build of the same source (the sanitizer test's)
+    if not path:
+        path = _LIB
+        if not os.path.exists(_LIB):
+            build()
+    lib = ctypes.CDLL(path)
     P64 = ctypes.POINTER(ctypes.POINTER(ctypes.c_int64))
     P32 = ctypes.POINTER(ctypes.POINTER(ctypes.c_int32))
     i32, i64, u64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double

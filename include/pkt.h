@@ -221,7 +221,8 @@ truss_status truss_edge_list(int32_t n, const int64_t* offsets, const int32_t* a
  * and have that property themselves, so the k-trusses are their connected
  * components (two such edges that share a vertex belong to the same k-truss).
  *   n, m             vertices and edges of the graph (n >= 0, 0 <= m < 2^31)
- *   el_u, el_v       device, int32[m]: edge endpoints, e.g. from truss_edge_list
+ *   el_u, el_v       device, int32[m]: edge endpoints in any order and orientation
+ *                    (e.g. from truss_edge_list); edge e is (el_u[e], el_v[e])
  *   trussness        device, int32[m], e.g. from truss_decompose
  *   k                >= 2
  *   label            device, int32[m] out: for an edge of trussness >= k, the

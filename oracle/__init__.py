@@ -57,9 +57,12 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB):
-        build()
-    lib = ctypes.CDLL(_LIB)
+    path = os.environ.get("PKT_ORACLE_LIB")  # another build of the same source (the sanitizer test's)
+    if not path:
+        path = _LIB
+        if not os.path.exists(_LIB):
+            build()
+    lib = ctypes.CDLL(path)
     vp = ctypes.c_void_p
     lib.oracle_check_csr.argtypes = [ctypes.c_int32, vp, vp]
     lib.oracle_check_csr.restype = ctypes.c_int

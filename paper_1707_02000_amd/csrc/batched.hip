@@ -24,6 +24,20 @@ using namespace pkt;
 
 namespace {
 
+// Structure of the batch, one thread per graph: both offset arrays start at 0,
+// every graph has at least its one offsets entry (n_g >= 0), an even slot count,
+// n_g <= 2^20 and m_g <= 2^24.  A graph with no offsets entry would shift every
+// later graph onto the previous one's vertices.
+__global__ __launch_bounds__(PKT_BLOCK) void k_batch_check(i32 G, const i64* __restrict__ vo,
+                                                          const i64* __restrict__ ao, u32* __restrict__ err) {
+  for (i64 g = (i64)blockIdx.x * PKT_BLOCK + threadIdx.x; g < G; g += (i64)gridDim.x * PKT_BLOCK) {
+    const i64 nv = vo[g + 1] - vo[g] - 1, two_m = ao[g + 1] - ao[g];
+    bool bad = nv < 0 || two_m < 0 || (two_m & 1) || nv > ((i64)1 << 20) || two_m > ((i64)2 << 24);
+    if (g == 0) bad = bad || vo[0] != 0 || ao[0] != 0;
+    if (bad) atomicOr(err, 1u);
+  }
+}
+
 // Union offsets: the offsets of graph g (local, n_g + 1 entries at vtx_off[g])
 // become global offsets adj_off[g] + local at union vertex vtx_off[g] - g + i.
 __global__ __launch_bounds__(PKT_BLOCK) void k_union_offsets(i32 G, const i64* __restrict__ vo, const i64* __restrict__ ao,
@@ -137,6 +151,24 @@ truss_status truss_decompose_batched(int32_t num_graphs, const int64_t* graph_vt
     set_error("graph offset arrays end at %lld / %lld, totals given %lld / %lld", (long long)ends[0],
               (long long)ends[1], (long long)total_vtx_entries, (long long)total_adj);
     return TRUSS_E_ARG;
+  }
+  {
+    // the per-graph structure, checked whatever opt.validate says: the union's vertex
+    // bases and the per-graph limits depend on it
+    Work w0;
+    work_layout(0, 0, false, workspace, &w0);
+    PKT_HIP(hipMemsetAsync(w0.verr, 0, sizeof(u32), s));
+    hipLaunchKernelGGL(k_batch_check, dim3(grid_for_b(num_graphs)), dim3(PKT_BLOCK), 0, s, num_graphs, graph_vtx_off,
+                       graph_adj_off, w0.verr);
+    PKT_LAUNCH_CHECK();
+    u32 bits = 0;
+    PKT_HIP(hipMemcpyAsync(&bits, w0.verr, sizeof(u32), hipMemcpyDeviceToHost, s));
+    PKT_HIP(hipStreamSynchronize(s));
+    if (bits) {
+      set_error("batch: graph offsets not starting at 0, a graph without its offsets entry, an odd slot count, "
+                "or a graph above n = 2^20 / m = 2^24");
+      return TRUSS_E_RANGE;
+    }
   }
 
   if (opt.batch_sequential) {

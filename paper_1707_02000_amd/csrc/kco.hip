@@ -309,6 +309,33 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_rl_rows(i32 n, i64 two_m, const u
     if (lower_bound_dev(keys, (i64)0, two_m, (u32)x) != off2[x]) atomicOr(&fl->err, 8u);
 }
 
+// Every slot's mirror: entry y in row x of the sorted pairs needs x in row y.
+// The row counts alone (k_rl_rows) pass an asymmetric CSR whose in- and
+// out-degrees agree at every vertex (a directed cycle), whose sorted pairs are then
+// its transpose; this check rejects it.  Rows are located per block chunk as in
+// k_rl_pairs.
+__global__ __launch_bounds__(PKT_BLOCK) void k_rl_mirror(i32 n, i64 two_m, const i64* __restrict__ off2,
+                                                        const i32* __restrict__ adj2, KoFlags* fl) {
+  __shared__ i64 rows[2];
+  const i64 chunks = (two_m + PKT_BLOCK - 1) / PKT_BLOCK;
+  for (i64 c = blockIdx.x; c < chunks; c += gridDim.x) {  // uniform over the block
+    const i64 j0 = c * PKT_BLOCK;
+    const i64 j1 = min(j0 + PKT_BLOCK, two_m) - 1;
+    if (threadIdx.x < 2)
+      rows[threadIdx.x] = upper_bound_dev(off2, (i64)0, (i64)n + 1, threadIdx.x == 0 ? j0 : j1) - 1;
+    __syncthreads();
+    const i64 j = j0 + threadIdx.x;
+    if (j <= j1) {
+      const i32 x = (i32)(upper_bound_dev(off2, rows[0], rows[1] + 1, j) - 1);
+      const i32 y = adj2[j];  // a vertex id: every value of the pairs is some new_id[u]
+      const i64 b = off2[y], e = off2[y + 1];
+      const i64 q = lower_bound_dev(adj2, b, e, x);
+      if (q == e || adj2[q] != x) atomicOr(&fl->err, 8u);
+    }
+    __syncthreads();  // rows[] is rewritten for the next chunk
+  }
+}
+
 size_t rl_layout(i64 two_m, void* ws, RsBufs* b, KoFlags** fl) {
   Carver cv(ws);
   RsBufs t;
@@ -517,6 +544,12 @@ extern "C" truss_status truss_kco_relabel(int32_t n, const int64_t* offsets, con
   PKT_LAUNCH_CHECK();
   if (two_m > 0) PKT_HIP(hipMemcpyAsync(adj2, b.v[q], sizeof(i32) * (size_t)two_m, hipMemcpyDeviceToDevice, s));
   if (truss_status st = read_flags(fl, &h, s)) return st;
+  if (!h.err && two_m > 0) {  // rows line up: every slot's mirror must be there too
+    hipLaunchKernelGGL(k_rl_mirror, dim3(grid_items(two_m)), dim3(PKT_BLOCK), 0, s, n, two_m,
+                       (const i64*)offsets2, (const i32*)adj2, fl);
+    PKT_LAUNCH_CHECK();
+    if (truss_status st = read_flags(fl, &h, s)) return st;
+  }
   if (h.err) {
     set_error("input CSR: (u, v) present without (v, u)");
     return TRUSS_E_NOT_SYMMETRIC;

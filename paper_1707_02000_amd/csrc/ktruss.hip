@@ -9,7 +9,7 @@
 // smaller one with a compare-and-swap (parents only ever decrease, so there are
 // no cycles and every find ends), finds halve their paths as they go; then one
 // pass points every vertex at its root, a second takes the smallest edge id of
-// every set (its root's first edge), and a third labels the edges with it.
+// every set, and a third labels the edges with it.
 #include <limits.h>
 
 #include "common.h"
@@ -77,12 +77,12 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_kt_compress(i32 n, i32* par) {
     par[v] = uf_find(par, (i32)v);
 }
 
-// Smallest edge id of every set.  A root is the smallest vertex of its set
-// (parents only decrease), so every edge of the set leaves from the root or from
-// a larger vertex, and in row-major edge order the smallest id is the root's
-// first edge: only edges whose lower endpoint is a root take part, and the lanes
-// of a wave that share one (consecutive edges of one row) take their minimum
-// first, so one atomic per wave and row reaches memory.
+// Smallest edge id of every set: every kept edge offers its id to its set's root
+// (par is fully compressed here, so par[u] is the root).  The edge list may come
+// in any order.  In the canonical row-major order the lanes of a wave mostly share
+// one root (consecutive edges of one row, or one large k-truss), so the lanes
+// that share the first active lane's root take their minimum first and one atomic
+// reaches memory for them; every other lane takes its own atomic.
 __global__ __launch_bounds__(PKT_BLOCK) void k_kt_first(i64 m, const i32* __restrict__ eu,
                                                        const i32* __restrict__ tau, i32 k,
                                                        const i32* __restrict__ par, i32* __restrict__ first,
@@ -92,19 +92,14 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_kt_first(i64 m, const i32* __rest
   const i64 m_up = (m + PKT_WAVE - 1) / PKT_WAVE * PKT_WAVE;  // whole waves stay in the loop
   for (i64 e = (i64)blockIdx.x * PKT_BLOCK + threadIdx.x; e < m_up; e += stride) {
     i32 r = -1;
-    if (e < m && tau[e] >= k) {
-      const i32 u = eu[e];
-      if (par[u] == u) r = u;
-    }
-    u64 todo = __ballot(r >= 0);
-    while (todo) {  // one round per distinct root among the lanes
-      const int lead = __ffsll((unsigned long long)todo) - 1;
-      const i32 rl = __shfl(r, lead);
-      const u64 same = __ballot(r == rl);
-      const i32 mn = wave_min_i32(r == rl ? (i32)e : INT_MAX);
-      if (lane_id() == lead) atomicMin(&first[rl], mn);
-      todo &= ~same;
-    }
+    if (e < m && tau[e] >= k) r = par[eu[e]];
+    const u64 act = __ballot(r >= 0);
+    if (act == 0) continue;
+    const int lead = __ffsll((unsigned long long)act) - 1;
+    const i32 rl = __shfl(r, lead);
+    const i32 mn = wave_min_i32(r == rl ? (i32)e : INT_MAX);
+    if (lane_id() == lead) atomicMin(&first[rl], mn);
+    if (r >= 0 && r != rl) atomicMin(&first[r], (i32)e);
   }
 }
 

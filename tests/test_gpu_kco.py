@@ -127,6 +127,13 @@ def test_edge_cases(gpu_lib):
     with pytest.raises(pkt.TrussError) as ei:  # not symmetric
         pkt.kco_relabel(np.array([0, 1, 1], np.int64), np.array([1], np.int32), ident[:2], ident[:2])
     assert ei.value.name == "TRUSS_E_NOT_SYMMETRIC"
+    with pytest.raises(pkt.TrussError) as ei:  # a directed 3-cycle: in- and out-degrees agree everywhere
+        pkt.kco_relabel(np.array([0, 1, 2, 3], np.int64), np.array([1, 2, 0], np.int32), ident[:3], ident[:3])
+    assert ei.value.name == "TRUSS_E_NOT_SYMMETRIC"
+    with pytest.raises(pkt.TrussError) as ei:  # the same under a non-trivial relabelling
+        pkt.kco_relabel(np.array([0, 1, 2, 3], np.int64), np.array([1, 2, 0], np.int32),
+                        np.array([2, 0, 1], np.int32), np.array([1, 2, 0], np.int32))
+    assert ei.value.name == "TRUSS_E_NOT_SYMMETRIC"
     off2, adj2 = pkt.kco_relabel(np.zeros(4, np.int64), np.zeros(0, np.int32), ident[:3], ident[:3])  # no edges
     assert off2.cpu().tolist() == [0, 0, 0, 0] and adj2.numel() == 0
     # mapping: an edge with no image, and a relabelled graph of another size

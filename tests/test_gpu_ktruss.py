@@ -95,3 +95,30 @@ def test_edge_cases(gpu_lib):
     lab, cnt = pkt.ktruss(3, np.array([[0, 1], [1, 2]], np.int32), np.array([2, 2], np.int32), 3)
     assert lab.cpu().tolist() == [-1, -1] and cnt == 0
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("order", ["reversed_endpoints", "shuffled", "shuffled_and_reversed"])
+def test_any_edge_order(gpu_lib, order):
+    """The edge list may come in any order and orientation: labels still name the
+    smallest edge id (in the given list) of every k-truss."""
+    import paper_1707_02000_amd as pkt
+
+    g = gg.workload("rmat16", seed=4)
+    tau = oracle.truss(g)
+    el = oracle.edge_list(g)
+    rng = np.random.default_rng(5)
+    perm = np.arange(g.m) if order == "reversed_endpoints" else rng.permutation(g.m)
+    el2 = el[perm].copy()
+    tau2 = tau[perm].copy()
+    if order != "shuffled":
+        flip = rng.random(g.m) < (1.0 if order == "reversed_endpoints" else 0.5)
+        el2[flip] = el2[flip][:, ::-1]
+    tmax = int(tau.max())
+    for k in (2, 3, tmax // 2, tmax):
+        lab, cnt = pkt.ktruss(g.n, el2, tau2, k)
+        want, wcnt = KT.labels(g.n, el2, tau2, k)
+        assert np.array_equal(lab.cpu().numpy(), want), (order, k)
+        assert cnt == wcnt
+    # the smallest case: one edge given as (1, 0)
+    lab, cnt = pkt.ktruss(2, np.array([[1, 0]], np.int32), np.array([2], np.int32), 2)
+    assert lab.cpu().tolist() == [0] and cnt == 1

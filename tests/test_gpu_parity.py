@@ -184,6 +184,16 @@ def test_batched_edge_cases(gpu_lib):
     with pytest.raises(gpu_lib.TrussError) as ei:
         gpu_lib.truss_decompose_batched(bad.vtx_off, bad.adj_off, bad.offsets, bad.adj)
     assert ei.value.name in ("TRUSS_E_RANGE", "TRUSS_E_NOT_SYMMETRIC", "TRUSS_E_NOT_SIMPLE")
+    # a graph with no offsets entry at all (it would shift the next graph onto this one's
+    # vertices), and graph offsets not starting at 0: rejected in every mode
+    ok = gg.pack([gg.from_edges(3, [(0, 1), (1, 2), (0, 2)]), gg.from_edges(3, [(0, 1), (1, 2), (0, 2)])])
+    for vo, ao in ((np.array([0, 4, 4, 8], np.int64), np.array([0, 6, 6, 12], np.int64)),
+                   (np.array([1, 5, 8], np.int64), ok.adj_off)):
+        offs = np.concatenate([ok.offsets, np.zeros(int(vo[-1]) - len(ok.offsets), np.int32)])
+        for seq in (False, True):
+            with pytest.raises(gpu_lib.TrussError) as ei:
+                gpu_lib.truss_decompose_batched(vo, ao, offs, ok.adj, validate=False, sequential=seq)
+            assert ei.value.name == "TRUSS_E_RANGE"
 
 
 def test_batched_full_config_sample(gpu_lib):
