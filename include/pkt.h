@@ -202,6 +202,25 @@ truss_status truss_decompose32(int32_t n, const int32_t* offsets, const int32_t*
                                truss_stats* stats, void* stream);
 
 /*
+ * truss_decompose32 with no allocation at all, for callers that cannot allocate
+ * (serving loops that must not call hipMalloc, harnesses that forbid allocation).
+ * The workspace is a static device array of 64 MiB (2^26 bytes) inside the
+ * library, one per GPU, held until the process ends: graphs whose
+ * truss_workspace_bytes(n, offsets[n]) + 8 * (n + 1) exceeds it are rejected with
+ * TRUSS_E_WORKSPACE (about 700 000 edges for sparse graphs).  The library calls
+ * no hipMalloc, hipFree, hipHostMalloc, event, stream or graph creation here: the
+ * loop state is read back into pageable host memory, device_loop 2 and 3 run as 1
+ * (device-driven steps), opt->trace and opt->profile are rejected (TRUSS_E_ARG)
+ * and the phase times in *stats stay 0.  Every call on one GPU uses that GPU's
+ * array: calls that overlap on one GPU (two host threads, or two streams) race
+ * and give undefined results.  Not for stream capture: the level loop reads its
+ * state back from the device.  Arguments, output and errors otherwise as
+ * truss_decompose32.
+ */
+truss_status truss_decompose32_static(int32_t n, const int32_t* offsets, const int32_t* adj, int32_t* trussness,
+                                      const truss_options* opt, truss_stats* stats, void* stream);
+
+/*
  * Initial support of every edge (number of triangles containing it), same
  * edge order, into support (device, int32[m]).  Same workspace as
  * truss_decompose.

@@ -128,6 +128,7 @@ _SIGS = {
                         + [ctypes.c_void_p] * 3),
     "truss_decompose32": (ctypes.c_int, [ctypes.c_int32] + [ctypes.c_void_p] * 4 + [ctypes.c_size_t]
                           + [ctypes.c_void_p] * 3),
+    "truss_decompose32_static": (ctypes.c_int, [ctypes.c_int32] + [ctypes.c_void_p] * 6),
     "truss_support": (ctypes.c_int, [ctypes.c_int32] + [ctypes.c_void_p] * 4 + [ctypes.c_size_t]
                       + [ctypes.c_void_p] * 2),
     "truss_edge_list": (ctypes.c_int, [ctypes.c_int32] + [ctypes.c_void_p] * 5 + [ctypes.c_size_t]
@@ -487,6 +488,27 @@ def kco_map(n, edges, new_id, offsets2, adj2, trussness2, *, stream=None):
     _check(lib.truss_kco_map(int(n), int(m), _ptr(eu), _ptr(ev), _ptr(nid), _ptr(off2), _ptr(adj2), _ptr(tau2),
                              _ptr(out), ctypes.c_void_p(wptr), nb.value, _stream(torch, stream)))
     return out[:m]
+
+
+def truss_decompose32_static(offsets, adj, *, validate=True, device_loop="device", stream=None, out=None,
+                             return_stats=False):
+    """truss_decompose32_static: int32 offsets, the library's static scratch as workspace
+    (no allocation inside the library); int32 [m] CUDA tensor.  ``out`` may be given
+    so that the call allocates nothing on the Python side either."""
+    torch = _torch()
+    lib = load()
+    off_t = _dev(offsets, torch.int32, torch)
+    adj_t = _dev(adj, torch.int32, torch)
+    n = off_t.numel() - 1
+    m = adj_t.numel() // 2
+    opt = make_options("auto", device_loop, validate)
+    if out is None:
+        out = torch.empty(max(m, 1), dtype=torch.int32, device="cuda")
+    st = Stats()
+    _check(lib.truss_decompose32_static(int(n), _ptr(off_t), _ptr(adj_t), _ptr(out), ctypes.byref(opt),
+                                        ctypes.byref(st), _stream(torch, stream)))
+    res = out[:m]
+    return (res, st.as_dict()) if return_stats else res
 
 
 def truss_decompose_batched(vtx_off, adj_off, offsets_packed, adj_packed, *, variant="auto", validate=True,

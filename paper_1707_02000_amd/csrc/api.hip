@@ -2,6 +2,8 @@
 #include <stdarg.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "truss.h"
 
 namespace pkt {
@@ -111,11 +113,94 @@ static truss_status decompose_common(i32 n, const OffT* offsets, const i32* adj,
   return run_single(w, opt, stats, out, s, support_only);
 }
 
+// ---- decomposition with no allocation at all
+// The workspace of truss_decompose32_static lives in this file-scope device array,
+// one copy per GPU, held until the process ends.  Host code never passes the
+// array's name (a host-side stand-in) to a kernel or a copy: it uses the device
+// address hipGetSymbolAddress gives for the current device, looked up once per
+// device.
+#define PKT_SCRATCH_BYTES ((size_t)64 << 20)
+static __device__ __align__(256) char scratch[PKT_SCRATCH_BYTES];
+
+#define PKT_SCRATCH_DEVICES 64
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[PKT_SCRATCH_DEVICES] = {nullptr};
+
+static truss_status scratch_of_current_device(void** out) {
+  int dev = 0;
+  PKT_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= PKT_SCRATCH_DEVICES) {
+    set_error("device %d is beyond the %d devices the static scratch serves", dev, PKT_SCRATCH_DEVICES);
+    return TRUSS_E_DEVICE;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)", __FILE__, __LINE__);
+    if (p == nullptr || ((uintptr_t)p & 255u)) {
+      set_error("static scratch at %p: not 256-byte aligned", p);
+      return TRUSS_E_INTERNAL;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return TRUSS_OK;
+}
+
+static truss_status decompose32_static(i32 n, const i32* offsets, const i32* adj, i32* out,
+                                       const truss_options* opt_in, truss_stats* stats, void* stream) {
+  set_error("");
+  truss_options opt;
+  truss_default_options(&opt);
+  if (opt_in) opt = *opt_in;
+  if (opt.trace || opt.profile) {
+    set_error("truss_decompose32_static takes no trace and no profile (both need host allocations)");
+    return TRUSS_E_ARG;
+  }
+  if (opt.device_loop == 2 || opt.device_loop == 3) opt.device_loop = 1;  // no graph, no mapped host slots
+  truss_status st = check_options(&opt);
+  if (st) return st;
+  if (n < 0 || offsets == nullptr) {
+    set_error("bad n or NULL offsets");
+    return TRUSS_E_ARG;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  i64 two_m = 0;
+  st = read_two_m(n, offsets, s, &two_m);
+  if (st) return st;
+  if (two_m > 0 && (adj == nullptr || out == nullptr)) {
+    set_error("NULL adj or output");
+    return TRUSS_E_ARG;
+  }
+  const size_t need = work_layout(n, two_m, true, nullptr, nullptr);
+  if (need > PKT_SCRATCH_BYTES) {
+    set_error("graph needs %zu bytes of workspace; the static scratch holds %zu (use truss_decompose32)", need,
+              PKT_SCRATCH_BYTES);
+    return TRUSS_E_WORKSPACE;
+  }
+  void* ws = nullptr;
+  st = scratch_of_current_device(&ws);
+  if (st) return st;
+  Work w;
+  work_layout(n, two_m, true, ws, &w);
+  w.adj = adj;
+  w.no_alloc = true;
+  st = prepare_off64(w, offsets, s);
+  if (st) return st;
+  return run_single(w, opt, stats, out, s, false);
+}
+
 }  // namespace pkt
 
 using namespace pkt;
 
 extern "C" {
+
+truss_status truss_decompose32_static(int32_t n, const int32_t* offsets, const int32_t* adj, int32_t* trussness,
+                                      const truss_options* opt, truss_stats* stats, void* stream) {
+  return decompose32_static(n, offsets, adj, trussness, opt, stats, stream);
+}
 
 void truss_default_options(truss_options* opt) {
   if (!opt) return;

@@ -1107,6 +1107,11 @@ struct Timer {
 thread_local Ctl* h_ctl_pinned = nullptr;
 
 truss_status read_ctl(const Work& w, Ctl* out, hipStream_t s) {
+  if (w.no_alloc) {  // pageable destination: nothing allocated
+    PKT_HIP(hipMemcpyAsync(out, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    PKT_HIP(hipStreamSynchronize(s));
+    return TRUSS_OK;
+  }
   if (!h_ctl_pinned) PKT_HIP(hipHostMalloc((void**)&h_ctl_pinned, sizeof(Ctl), hipHostMallocDefault));
   PKT_HIP(hipMemcpyAsync(h_ctl_pinned, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
   PKT_HIP(hipStreamSynchronize(s));
@@ -1395,7 +1400,7 @@ struct StepGraph {
 truss_status run_single(const Work& w, const truss_options& opt, truss_stats* stats, i32* trussness,
                         hipStream_t s, bool support_only) {
   Timer tm;
-  tm.init(stats != nullptr, s);
+  tm.init(stats != nullptr && !w.no_alloc, s);  // phase times need events
   tm.mark();  // 0
   Ctl init;
   memset(&init, 0, sizeof(init));

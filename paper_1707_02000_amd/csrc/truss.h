@@ -88,6 +88,7 @@ struct Work {
   i32* oeid;        // [m] (aliases ceid[1])
   Ctl* ctl;
   u32* verr;        // validation error bits
+  bool no_alloc;    // host side allocates nothing: pageable readbacks, no events or graphs
 };
 
 size_t work_layout(i32 n, i64 two_m, bool off32, void* base, Work* w);
