@@ -69,7 +69,10 @@ typedef enum {
                                     (one binary search per shorter-row entry), then finalize */
   TRUSS_CHOICE_WIDE_NARROW = 3,  /* the same with 256 blocks */
   TRUSS_CHOICE_WIDE_GALLOP = 4,  /* wide, 8 shorter-row entries per item, galloping search */
-  TRUSS_NUM_CHOICES = 5
+  TRUSS_CHOICE_WAVE = 5,         /* one wave per frontier edge, no work scan: the two rows merged
+                                    in 64-entry chunks (binary search in the longer row when it is
+                                    over 8 times the shorter), then finalize */
+  TRUSS_NUM_CHOICES = 6
 } truss_choice;
 
 /* Policy that picks the launch of every round. */
@@ -80,8 +83,8 @@ typedef enum {
   TRUSS_VARIANT_FIXED = 3,   /* every round uses truss_options.force_choice (where valid) */
   TRUSS_VARIANT_LEARNED = 4  /* the MLP cost model (truss_options.mlp_weights) predicts the time
                                 of every valid choice from the frontier's features (frontiers of
-                                more than 256 edges); the cheapest is launched when it is predicted
-                                at least 25 % faster than the heuristic's launch, which stands
+                                more than 2048 edges); the cheapest is launched when it is predicted
+                                at least 10 % faster than the heuristic's launch, which stands
                                 otherwise and for smaller frontiers */
 } truss_variant;
 
@@ -94,7 +97,8 @@ typedef enum {
 /* One record per launch sequence of the peeling loop (when tracing). */
 typedef struct {
   int32_t level;             /* support level at the start */
-  int32_t kind;              /* 0 level scan, 1 fused launch, 2 wide launch sequence */
+  int32_t kind;              /* 0 level scan, 1 fused launch, 2 wide launch sequence, 3 one wave
+                                per edge */
   int32_t choice;            /* truss_choice launched (kinds 1 and 2) */
   int32_t rounds;            /* frontier rounds completed by the sequence */
   int64_t frontier;          /* frontier size at the start */
@@ -134,9 +138,11 @@ typedef struct {
   truss_trace* trace;        /* host: per-sequence trace of the peeling loop, or NULL */
   int32_t profile;           /* 1 = time every launch of the wide sub-level kernel with events
                                 (truss_stats.wide_ms) */
-  int32_t batch_sequential;  /* truss_decompose_batched: 1 = one graph after another through the
-                                single-graph path (a comparison point); 0 = all graphs at once as
-                                one disjoint union (default) */
+  int32_t batch_mode;        /* truss_decompose_batched: 0 = all graphs at once as one disjoint
+                                union through one level loop; 1 = one graph after another
+                                through the single-graph path (a comparison point); 2 = one
+                                persistent launch, one workgroup per graph from a queue ordered
+                                by decreasing edge count (default) */
   int32_t force_choice;      /* truss_choice for TRUSS_VARIANT_FIXED */
   int32_t single_round;      /* 1 = every launch sequence runs exactly one frontier round (no
                                 continuation of tiny rounds inside the fused launch); for
@@ -144,6 +150,7 @@ typedef struct {
   int32_t* peel_round;       /* device, int32[m], or NULL: receives for every edge the index of the
                                 frontier round that processed it (a peeling order: rounds run in
                                 level order, so a lower trussness never gets a later round) */
+  int32_t reserved[8];       /* zero (room for later options without a layout change) */
 } truss_options;
 
 typedef struct {
@@ -158,7 +165,8 @@ typedef struct {
   float ms_support;
   float ms_peel;         /* level loop: scans, sub-levels, compactions */
   float ms_total;
-  int64_t choice_count[5];  /* launch sequences run with each truss_choice */
+  int64_t choice_count[8];  /* launch sequences run with each truss_choice (first
+                               TRUSS_NUM_CHOICES used) */
   /* the wide sub-level intersection kernel (the dominant kernel) */
   int64_t wide_launches;   /* launches that found work */
   int64_t wide_items;      /* intersection items (one per shorter-row entry searched) */
@@ -424,8 +432,8 @@ truss_status truss_mlp_train(const float* X, const float* T, const float* M, int
                              float lr, float* loss_history, void* workspace, size_t workspace_bytes, void* stream);
 
 /* The peeling loop's decision for n frontiers: choice[i] = the valid choice of
- * least predicted time if it beats the heuristic's launch by 25 % (log2 margin
- * 0.32), else the heuristic's launch (fused choices are valid up to 2048 frontier
+ * least predicted time if it beats the heuristic's launch by 10 % (log2 margin
+ * 0.1375), else the heuristic's launch (fused choices are valid up to 2048 frontier
  * edges, ncurr gives each frontier's size); Y (or NULL) receives the predictions.
  * Uses the same device inference and decision routines as the loop. */
 truss_status truss_mlp_choose(const float* X, const int32_t* ncurr, int32_t n, const float* weights, int32_t* choice,

@@ -85,7 +85,7 @@ def gradient(w, X, T, M, k):
     return out
 
 
-MARGIN = float(np.log2(1.25))  # the decision departs from the heuristic only for a 25 % predicted gain
+MARGIN = float(np.log2(1.10))  # the decision departs from the heuristic only for a 10 % predicted gain
 
 
 def choose(w, X, ncurr, k, fused=(0, 1), fused_limit=2048, heuristic_limit=2048, margin=MARGIN):

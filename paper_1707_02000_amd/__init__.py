@@ -23,7 +23,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpkt.so")
 
 VARIANTS = {"auto": 0, "bsearch": 1, "merge": 2, "fixed": 3, "learned": 4}
-CHOICES = ["fused", "fused_narrow", "wide", "wide_narrow", "wide_gallop"]
+CHOICES = ["fused", "fused_narrow", "wide", "wide_narrow", "wide_gallop", "wave"]
 LOOP_MODES = {"host": 0, "device": 1, "graph": 2, "pipelined": 3}  # truss_options.device_loop
 
 
@@ -60,10 +60,11 @@ class Options(ctypes.Structure):
         ("mlp_weights", ctypes.c_void_p),
         ("trace", ctypes.c_void_p),
         ("profile", ctypes.c_int32),
-        ("batch_sequential", ctypes.c_int32),
+        ("batch_mode", ctypes.c_int32),
         ("force_choice", ctypes.c_int32),
         ("single_round", ctypes.c_int32),
         ("peel_round", ctypes.c_void_p),
+        ("reserved", ctypes.c_int32 * 8),
     ]
 
 
@@ -80,7 +81,7 @@ class Stats(ctypes.Structure):
         ("ms_support", ctypes.c_float),
         ("ms_peel", ctypes.c_float),
         ("ms_total", ctypes.c_float),
-        ("choice_count", ctypes.c_int64 * 5),
+        ("choice_count", ctypes.c_int64 * 8),
         ("wide_launches", ctypes.c_int64),
         ("wide_items", ctypes.c_int64),
         ("wide_frontier", ctypes.c_int64),
@@ -90,7 +91,7 @@ class Stats(ctypes.Structure):
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("choice_count",)}
-        d["choice_count"] = list(self.choice_count)
+        d["choice_count"] = list(self.choice_count)[:len(CHOICES)]
         return d
 
 
@@ -511,10 +512,17 @@ def truss_decompose32_static(offsets, adj, *, validate=True, device_loop="device
     return (res, st.as_dict()) if return_stats else res
 
 
+BATCH_MODES = {"union": 0, "sequential": 1, "persistent": 2}  # truss_options.batch_mode
+
+
 def truss_decompose_batched(vtx_off, adj_off, offsets_packed, adj_packed, *, variant="auto", validate=True,
-                            sequential=False, stream=None, workspace=None, out=None, return_stats=False,
-                            device_loop="pipelined", mlp_weights=None):
-    """Trussness of many packed graphs (layout of include/pkt.h); int32 [sum m_g] CUDA tensor."""
+                            mode="persistent", sequential=False, stream=None, workspace=None, out=None,
+                            return_stats=False, device_loop="pipelined", mlp_weights=None, force_choice=None):
+    """Trussness of many packed graphs (layout of include/pkt.h); int32 [sum m_g] CUDA tensor.
+
+    mode: "persistent" (one launch, a workgroup per graph), "union" (one level loop over the
+    disjoint union) or "sequential" (one graph after another); sequential=True is the same
+    as mode="sequential"."""
     torch = _torch()
     lib = load()
     vo = _dev(vtx_off, torch.int64, torch)
@@ -523,8 +531,8 @@ def truss_decompose_batched(vtx_off, adj_off, offsets_packed, adj_packed, *, var
     ap = _dev(adj_packed, torch.int32, torch)
     G = vo.numel() - 1
     total_vtx, total_adj = int(op.numel()), int(ap.numel())
-    opt = make_options(variant, device_loop, validate, mlp_weights=mlp_weights)
-    opt.batch_sequential = int(bool(sequential))
+    opt = make_options(variant, device_loop, validate, mlp_weights=mlp_weights, force_choice=force_choice)
+    opt.batch_mode = BATCH_MODES["sequential" if sequential else mode]
     if workspace is None:
         nb = ctypes.c_size_t(0)
         _check(lib.truss_batched_workspace_bytes(G, total_vtx, total_adj, ctypes.byref(opt), ctypes.byref(nb)))

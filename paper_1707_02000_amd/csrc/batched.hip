@@ -1,13 +1,13 @@
-// Batched decomposition of many independent graphs.
-//
-// Trussness is a property of each connected component, and the edge order of the
-// output (row-major, per graph, graphs back to back) is exactly the edge order of
-// the disjoint union of the graphs with vertex ids shifted by the graph's vertex
-// base.  So the batch is decomposed as one union graph: one level loop, one
-// sequence of launches for every graph at once, through the same kernels as a
-// single graph.  The option `batch_sequential` instead runs one graph after
-// another through the single-graph path (the comparison point for the batched
-// mode).
+// Batched decomposition of many independent graphs, three ways (truss_options::
+// batch_mode):
+//   2 (default) one persistent launch, every workgroup decomposing whole graphs
+//     taken from a queue ordered by decreasing size (persist.hip);
+//   0 the disjoint union: trussness is a property of each connected component, and
+//     the edge order of the output (row-major, per graph, graphs back to back) is
+//     exactly the edge order of the disjoint union of the graphs with vertex ids
+//     shifted by the graph's vertex base, so the batch is decomposed as one union
+//     graph: one level loop, one sequence of launches for every graph at once;
+//   1 one graph after another through the single-graph path (a comparison point).
 #include <string.h>
 
 #include <vector>
@@ -18,6 +18,10 @@ namespace pkt {
 truss_status run_single(const Work& w, const truss_options& opt, truss_stats* stats, i32* trussness,
                         hipStream_t s, bool support_only);
 truss_status prepare_off64(Work& w, const i32* off32, hipStream_t s);
+size_t persist_workspace_bytes(i32 G, i64 total_vtx, i64 total_adj);
+truss_status run_persistent(i32 G, const i64* d_vo, const i64* d_ao, const i32* offs, const i32* adj, i32* out,
+                            const std::vector<i64>& vo, const std::vector<i64>& ao, void* ws, const truss_options& opt,
+                            truss_stats* stats, hipStream_t s);
 }  // namespace pkt
 
 using namespace pkt;
@@ -111,7 +115,9 @@ truss_status truss_batched_workspace_bytes(int32_t num_graphs, int64_t total_vtx
   // the sequential mode reuses one single-graph workspace (int32 offsets converted)
   const size_t seq = work_layout((i32)n_union, total_adj, true, nullptr, nullptr);
   const size_t uni = single + union_bytes(n_union, total_adj);
+  const size_t per = persist_workspace_bytes(num_graphs, total_vtx_entries, total_adj);
   *bytes = uni > seq ? uni : seq;
+  if (per > *bytes) *bytes = per;
   return TRUSS_OK;
 }
 
@@ -171,7 +177,19 @@ truss_status truss_decompose_batched(int32_t num_graphs, const int64_t* graph_vt
     }
   }
 
-  if (opt.batch_sequential) {
+  if (opt.batch_mode < 0 || opt.batch_mode > 2) {
+    set_error("batch_mode must be 0 (union), 1 (sequential) or 2 (persistent)");
+    return TRUSS_E_ARG;
+  }
+  if (opt.batch_mode == 2) {
+    std::vector<i64> vo(num_graphs + 1), ao(num_graphs + 1);
+    PKT_HIP(hipMemcpyAsync(vo.data(), graph_vtx_off, sizeof(i64) * (num_graphs + 1), hipMemcpyDeviceToHost, s));
+    PKT_HIP(hipMemcpyAsync(ao.data(), graph_adj_off, sizeof(i64) * (num_graphs + 1), hipMemcpyDeviceToHost, s));
+    PKT_HIP(hipStreamSynchronize(s));
+    return run_persistent(num_graphs, graph_vtx_off, graph_adj_off, offsets_packed, adj_packed, trussness_packed, vo,
+                          ao, workspace, opt, stats, s);
+  }
+  if (opt.batch_mode == 1) {
     // one graph after another through the single-graph path
     std::vector<i64> vo(num_graphs + 1), ao(num_graphs + 1);
     PKT_HIP(hipMemcpyAsync(vo.data(), graph_vtx_off, sizeof(i64) * (num_graphs + 1), hipMemcpyDeviceToHost, s));

@@ -11,10 +11,10 @@
 #include "common.h"
 
 // The learned decision departs from the heuristic's launch only when the model
-// predicts the other launch at least 25 % faster: log2(1.25) in the model's units
+// predicts the other launch at least 10 % faster: log2(1.1) in the model's units
 // (log2 microseconds).  Near the heuristic's threshold the two launches cost about
 // the same and the model's error would otherwise flip them back and forth.
-#define MLP_MARGIN 0.32192809f
+#define MLP_MARGIN 0.13750352f
 
 #define MLP_IN 6
 #define MLP_H 64
@@ -35,6 +35,10 @@
 // Forward pass of one feature vector by one block (blockDim.x >= MLP_H).
 // x: raw features (LDS or registers of thread 0 copied to LDS), y: outputs
 // (LDS, MLP_OUT), ha/hb: LDS scratch of MLP_H floats each.  All threads call it.
+// Unit j walks its inputs from i = j (rotated): at every step the units of a wave
+// read weights j * MLP_H + (i + j) % MLP_H, which fall in distinct LDS banks,
+// where the plain order (every unit reading column i at once, a stride of
+// MLP_H words) hits a single bank.
 __device__ __forceinline__ void mlp_forward_block(const float* __restrict__ W, const float* x, float* y, float* ha,
                                                   float* hb) {
   const int j = threadIdx.x;
@@ -50,19 +54,31 @@ __device__ __forceinline__ void mlp_forward_block(const float* __restrict__ W, c
   __syncthreads();
   if (j < MLP_H) {
     float s = W[MLP_OFF_B2 + j];
-    for (int i = 0; i < MLP_H; ++i) s = fmaf(W[MLP_OFF_W2 + j * MLP_H + i], ha[i], s);
+#pragma unroll 8
+    for (int k = 0; k < MLP_H; ++k) {
+      const int i = (k + j) & (MLP_H - 1);
+      s = fmaf(W[MLP_OFF_W2 + j * MLP_H + i], ha[i], s);
+    }
     hb[j] = fmaxf(s, 0.f);
   }
   __syncthreads();
   if (j < MLP_H) {
     float s = W[MLP_OFF_B3 + j];
-    for (int i = 0; i < MLP_H; ++i) s = fmaf(W[MLP_OFF_W3 + j * MLP_H + i], hb[i], s);
+#pragma unroll 8
+    for (int k = 0; k < MLP_H; ++k) {
+      const int i = (k + j) & (MLP_H - 1);
+      s = fmaf(W[MLP_OFF_W3 + j * MLP_H + i], hb[i], s);
+    }
     ha[j] = fmaxf(s, 0.f);
   }
   __syncthreads();
   if (j < MLP_OUT) {
     float s = W[MLP_OFF_B4 + j];
-    for (int i = 0; i < MLP_H; ++i) s = fmaf(W[MLP_OFF_W4 + j * MLP_H + i], ha[i], s);
+#pragma unroll 8
+    for (int k = 0; k < MLP_H; ++k) {
+      const int i = (k + j) & (MLP_H - 1);
+      s = fmaf(W[MLP_OFF_W4 + j * MLP_H + i], ha[i], s);
+    }
     y[j] = s;
   }
   __syncthreads();

@@ -36,75 +36,10 @@
 
 #include "mlp.h"
 #include "peel.h"
+#include "psl.h"
 #include "scan.h"
 
 namespace {
-
-// ---------------------------------------------------------------- decrement rule
-
-// Decrement rule for edge x of a triangle whose other non-frontier-edge is y,
-// seen from frontier edge e1 in round r: x loses one unit if its support is
-// above l and e1 owns the triangle (y is not in the frontier, or e1 has the
-// lower id -- the higher id with owner_higher).  The atomic's old value decides:
-// l + 1 means x now sits at l and joins the next frontier (tag of round r + 1);
-// <= l means the decrement overshot (another thread got there first) and is
-// undone.  The caller's earlier read of x's word may be stale: while the support
-// is > l every older value is > l too, and once it is <= l it stays <= l for the
-// level, so a stale read can only cause a decrement that is then undone.  Whether
-// y is current comes from the same earlier read of y's word: during a round a
-// state only changes between values that are not the round's tag (alive -> next,
-// previous round -> processed), so that read answers for the whole round.  The
-// next-frontier tag written here reads as "not current" and "not processed" to
-// every other thread.
-//
-// Applied to both other edges es, eo of one triangle (words ws, wo as read by the
-// caller): (x, y) = (es, eo) and (eo, es), both atomics issued before either
-// result is used, so their round trips overlap.  xa / xb get es / eo if they
-// joined the next frontier, else -1.
-__device__ __forceinline__ void psl_tri(i32 es, i32 ws, i32 eo, i32 wo, i32 e1, i32 l, i32 r, i32* sw, i32* order,
-                                        int owner_higher, i32& xa, i32& xb) {
-  const u8 tcur = round_tag(r);
-  const bool own_s = sw_st(wo) != tcur || (owner_higher ? (e1 > eo) : (e1 < eo));
-  const bool own_o = sw_st(ws) != tcur || (owner_higher ? (e1 > es) : (e1 < es));
-  const bool ds = own_s && sw_sup(ws) > l, dd = own_o && sw_sup(wo) > l;
-  const i32 as = ds ? sw_sup(atomicSub(&sw[es], SW_ONE)) : 0;
-  const i32 ao = dd ? sw_sup(atomicSub(&sw[eo], SW_ONE)) : 0;
-  xa = xb = -1;
-  if (ds) {
-    if (as == l + 1) {
-      atomicOr(&sw[es], (i32)round_tag(r + 1));
-      if (order) order[es] = r + 1;
-      xa = es;
-    } else if (as <= l) {
-      atomicAdd(&sw[es], SW_ONE);
-    }
-  }
-  if (dd) {
-    if (ao == l + 1) {
-      atomicOr(&sw[eo], (i32)round_tag(r + 1));
-      if (order) order[eo] = r + 1;
-      xb = eo;
-    } else if (ao <= l) {
-      atomicAdd(&sw[eo], SW_ONE);
-    }
-  }
-}
-
-// Shorter and longer working rows of frontier edge e1 = (u, v).
-struct Rows {
-  i64 sb, slen, lb, le;
-};
-
-__device__ __forceinline__ Rows rows_of(const Csr& c, int2 uv) {
-  const i64 ub = c.off[uv.x], ue = c.off[uv.x + 1], vb = c.off[uv.y], ve = c.off[uv.y + 1];
-  Rows r;
-  if (ue - ub <= ve - vb) {
-    r.sb = ub; r.slen = ue - ub; r.lb = vb; r.le = ve;
-  } else {
-    r.sb = vb; r.slen = ve - vb; r.lb = ub; r.le = ue;
-  }
-  return r;
-}
 
 // Shorter-row entries handled by one item: 1 (binary search per entry) or
 // GALLOP_K (one binary search, then galloping forward in the longer row).
@@ -147,7 +82,10 @@ __device__ __forceinline__ int log2_bin(i64 d) { return 63 - __clzll((unsigned l
 #define FEAT_SAMPLE 512  // frontier edges sampled (evenly spaced) for the features
 
 __device__ __forceinline__ bool is_fused(int c) { return c == TRUSS_CHOICE_FUSED || c == TRUSS_CHOICE_FUSED_NARROW; }
-__device__ __forceinline__ bool is_wide(int c) { return c >= TRUSS_CHOICE_WIDE && c < TRUSS_NUM_CHOICES; }
+__device__ __forceinline__ bool is_wide(int c) {
+  return c == TRUSS_CHOICE_WIDE || c == TRUSS_CHOICE_WIDE_NARROW || c == TRUSS_CHOICE_WIDE_GALLOP;
+}
+__device__ __forceinline__ bool is_wave(int c) { return c == TRUSS_CHOICE_WAVE; }
 
 // The built-in heuristic: fused launch up to FUSED_THRESHOLD frontier edges (the
 // threshold the tuner's trace search picked), else the wide sequence.
@@ -1035,6 +973,44 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_psl_bsearch(PeelArgs a, const 
   ba.flush(next, &ctl->nnext);
 }
 
+// Round of one wave per frontier edge (TRUSS_CHOICE_WAVE): no work prefix and no
+// scan launches; wave g of the grid takes frontier edges g, g + waves, ... and
+// merges (or, for skewed rows, searches) the edge's two rows itself (wave_edge:
+// coalesced row loads, the 64-entry chunks located among each other by lane
+// shuffles).  k_decide follows and ends the round.
+struct WaveAppend {
+  BlockAppend* ba;
+  i32* next;
+  i32* counter;
+  __device__ __forceinline__ void add(i32 x0, i32 x1) { ba->add(x0, x1, next, counter); }
+};
+
+__global__ __launch_bounds__(WIDE_THREADS) void k_psl_wave(PeelArgs a) {
+  Ctl* ctl = a.ctl;
+  __shared__ CtlView v;
+  __shared__ BlockAppend ba;
+  load_view(ctl, &v);
+  if (v.done || v.ncurr == 0 || !is_wave(v.choice)) return;
+  const i32 nc = v.ncurr, l = v.level, sel = v.sel, r = v.r;
+  const i32* curr = cur_of(a, sel);
+  i32* next = next_of(a, sel);
+  const Csr c = a.csr.pick(v.csel);
+  mark_prev(a, sel, r, v.nprev, (i64)blockIdx.x * WIDE_THREADS + threadIdx.x, (i64)gridDim.x * WIDE_THREADS);
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->round_done = 1;
+  if (threadIdx.x == 0) ba.n = 0;
+  __syncthreads();
+  WaveAppend app{&ba, next, &ctl->nnext};
+  if (l > 0) {  // level 0: frontier edges lie in no triangle
+    constexpr int WPB = WIDE_THREADS / PKT_WAVE;
+    const i64 waves = (i64)gridDim.x * WPB;
+    for (i64 i = (i64)blockIdx.x * WPB + threadIdx.x / PKT_WAVE; i < nc; i += waves) {
+      const i32 e1 = curr[i];
+      wave_edge(c, rows_of(c, a.el[e1]), e1, l, r, a.sw, a.order, a.owner_higher, app);
+    }
+  }
+  ba.flush(next, &ctl->nnext);
+}
+
 // One block after a level scan or a round: ends the round the previous launch
 // ran (Ctl::round_done), goes on alone while the work stays small, then picks
 // the launch of the frontier left, if any (only when none is picked yet).
@@ -1220,6 +1196,10 @@ static truss_status launch_round(const Work& w, const PeelArgs& a, const Ctl& hc
     const int blocks = hc.choice == TRUSS_CHOICE_FUSED ? FUSED_BLOCKS : FUSED_NARROW_BLOCKS;
     hipLaunchKernelGGL(k_psl_small, dim3(blocks), dim3(SMALL_THREADS), 0, s, a);
     hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a, (i64)0, 0);
+  } else if (hc.choice == TRUSS_CHOICE_WAVE) {
+    *kind = 3;
+    hipLaunchKernelGGL(k_psl_wave, dim3(WIDE_BLOCKS), dim3(WIDE_THREADS), 0, s, a);
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a, (i64)0, 0);
   } else {
     *kind = 2;
     // level 0: frontier edges lie in no triangle, nothing to intersect or scan
@@ -1252,6 +1232,7 @@ static truss_status enqueue_step(const Work& w, const PeelArgs& a, int G, hipStr
   if (prof) PKT_HIP(prof->mark(s));
   hipLaunchKernelGGL(k_psl_bsearch, dim3(WIDE_BLOCKS), dim3(WIDE_THREADS), 0, s, a, (const i64*)w.X);
   if (prof) PKT_HIP(prof->mark(s));
+  hipLaunchKernelGGL(k_psl_wave, dim3(WIDE_BLOCKS), dim3(WIDE_THREADS), 0, s, a);
   PKT_LAUNCH_CHECK();
   return TRUSS_OK;
 }
@@ -1265,7 +1246,7 @@ static truss_status enqueue_step(const Work& w, const PeelArgs& a, int G, hipStr
 // work prefix of a wide round, the chunk offsets of a level scan) comes from the
 // launch just before it in the same sequence, under the same loop state.
 
-enum SeqKind { SEQ_SCAN = 0, SEQ_DECIDE = 1, SEQ_FUSED = 2, SEQ_WIDE = 3 };
+enum SeqKind { SEQ_SCAN = 0, SEQ_DECIDE = 1, SEQ_FUSED = 2, SEQ_WIDE = 3, SEQ_WAVE = 4 };
 
 #define PIPE_DEPTH 2  // sequences in flight beyond the last state seen (default; measured best)
 #define PIPE_MAX 6
@@ -1275,6 +1256,7 @@ inline int seq_kind(i32 ncurr, i32 choice) {
   if (ncurr == 0) return SEQ_SCAN;
   if (choice == CHOICE_NONE) return SEQ_DECIDE;
   if (choice == TRUSS_CHOICE_FUSED || choice == TRUSS_CHOICE_FUSED_NARROW) return SEQ_FUSED;
+  if (choice == TRUSS_CHOICE_WAVE) return SEQ_WAVE;
   return SEQ_WIDE;
 }
 
@@ -1292,6 +1274,8 @@ static truss_status enqueue_seq(const Work& w, const PeelArgs& a, int kind, int 
   } else if (kind == SEQ_FUSED) {
     const int blocks = choice == TRUSS_CHOICE_FUSED_NARROW ? FUSED_NARROW_BLOCKS : FUSED_BLOCKS;
     hipLaunchKernelGGL(k_psl_small, dim3(blocks), dim3(SMALL_THREADS), 0, s, a);
+  } else if (kind == SEQ_WAVE) {
+    hipLaunchKernelGGL(k_psl_wave, dim3(WIDE_BLOCKS), dim3(WIDE_THREADS), 0, s, a);
   } else if (kind == SEQ_WIDE) {
     PKT_HIP((scan_launch<WideLen, true>(WideLen{a}, w.partial, w.X, &w.ctl->scan_arrive, s)));
     const int blocks = choice == TRUSS_CHOICE_WIDE_NARROW ? WIDE_NARROW_BLOCKS : WIDE_BLOCKS;
@@ -1493,7 +1477,9 @@ truss_status run_single(const Work& w, const truss_options& opt, truss_stats* st
         }
       while (nfl < depth) {
         const i64 q = ++snap_seq;
-        const int choice = known ? cur.choice : (ks == SEQ_FUSED ? TRUSS_CHOICE_FUSED : TRUSS_CHOICE_WIDE);
+        const int choice = known ? cur.choice
+                                 : (ks == SEQ_FUSED ? TRUSS_CHOICE_FUSED
+                                                    : (ks == SEQ_WAVE ? TRUSS_CHOICE_WAVE : TRUSS_CHOICE_WIDE));
         truss_status r = enqueue_seq(w, a, ks, choice, cur.nalive, s, prof, q);
         if (r) return r;
         fl[nfl++] = Flight{q, ks};
@@ -1518,7 +1504,7 @@ truss_status run_single(const Work& w, const truss_options& opt, truss_stats* st
       }
       if (f.kind == SEQ_SCAN && seq_kind(prev.ncurr, prev.choice) == SEQ_SCAN) {
         const int k = seq_kind(cur.ncurr, cur.choice);
-        if (k == SEQ_FUSED || k == SEQ_WIDE) after_scan = k;
+        if (k == SEQ_FUSED || k == SEQ_WIDE || k == SEQ_WAVE) after_scan = k;
       }
       if (opt.compact && cur.compact) {
         PKT_HIP(hipStreamSynchronize(s));  // lets the sequences in flight finish

@@ -164,7 +164,7 @@ def choose_batch(W, X, ncurr):
     return C.cpu().numpy(), Y.cpu().numpy()
 
 
-LEARNED_MIN_FRONTIER = 256  # the library consults the model above this frontier size
+LEARNED_MIN_FRONTIER = 2048  # the library consults the model above this frontier size
 
 
 def learned_choices(W, rounds):

@@ -58,7 +58,9 @@ def small_graphs():
 @pytest.mark.parametrize("name,g", list(small_graphs()))
 def test_small_graphs(gpu_lib, name, g):
     say("case", name, "n", g.n, "m", g.m)
-    assert np.array_equal(gpu_tau(gpu_lib, g), oracle.truss(g))
+    want = oracle.truss(g)
+    assert np.array_equal(gpu_tau(gpu_lib, g), want)
+    assert np.array_equal(gpu_tau(gpu_lib, g, force_choice="wave"), want)
 
 
 @pytest.mark.parametrize("make", [
@@ -106,6 +108,12 @@ def test_support_and_edge_list(gpu_lib, make):
     dict(device_loop="pipelined", force_choice="fused_narrow"),
     dict(device_loop="pipelined", variant="merge", profile=True),
     dict(device_loop="pipelined", compact=False),
+    dict(force_choice="wave"),
+    dict(force_choice="wave", owner_rule=1),
+    dict(device_loop="host", force_choice="wave"),
+    dict(device_loop="graph", force_choice="wave"),
+    dict(device_loop="device", force_choice="wave", steps_per_sync=2),
+    dict(device_loop="pipelined", force_choice="wave", compact=False),
 ])
 def test_medium_graphs(gpu_lib, make, opts):
     g = make()
@@ -160,39 +168,50 @@ def test_malformed_inputs_rejected(gpu_lib):
     assert ei.value.name in ("TRUSS_E_ARG", "TRUSS_E_RANGE")
 
 
-@pytest.mark.parametrize("sequential", [False, True])
-def test_batched_matches_oracle(gpu_lib, sequential):
+@pytest.mark.parametrize("mode", ["union", "sequential", "persistent"])
+def test_batched_matches_oracle(gpu_lib, mode):
     b = gg.batch(24, 64, 700, seed=11)
-    say("case batch24", b.total_m, "sequential", sequential)
-    tau = gpu_lib.truss_decompose_batched(b.vtx_off, b.adj_off, b.offsets, b.adj,
-                                          sequential=sequential).cpu().numpy()
+    say("case batch24", b.total_m, "mode", mode)
+    tau = gpu_lib.truss_decompose_batched(b.vtx_off, b.adj_off, b.offsets, b.adj, mode=mode).cpu().numpy()
     for i in range(b.num_graphs):
         g = b.graph(i)
         s = int(b.adj_off[i]) // 2
         assert np.array_equal(tau[s:s + g.m], oracle.truss(g)), i
 
 
-def test_batched_edge_cases(gpu_lib):
+@pytest.mark.parametrize("mode", ["union", "sequential", "persistent"])
+def test_batched_edge_cases(gpu_lib, mode):
     graphs = [gg.from_edges(0, []), gg.from_edges(5, []), gg.from_edges(3, [(0, 1), (1, 2), (0, 2)]),
-              gg.from_edges(1, []), gg.rmat(9, 8, seed=2), gg.from_edges(4, itertools.combinations(range(4), 2))]
+              gg.from_edges(1, []), gg.rmat(9, 8, seed=2), gg.from_edges(4, itertools.combinations(range(4), 2)),
+              gg.from_edges(120, itertools.combinations(range(120), 2)),  # K_120: above the LDS support limit
+              gg.from_edges(2, [(0, 1)])]
     b = gg.pack(graphs)
-    tau = gpu_lib.truss_decompose_batched(b.vtx_off, b.adj_off, b.offsets, b.adj).cpu().numpy()
+    tau = gpu_lib.truss_decompose_batched(b.vtx_off, b.adj_off, b.offsets, b.adj, mode=mode).cpu().numpy()
     want = np.concatenate([oracle.truss(g) for g in graphs])
     assert np.array_equal(tau, want)
     bad = gg.pack([gg.from_edges(3, [(0, 1)]), gg.from_edges(2, [(0, 1)])])
     bad.adj[0] = 5  # local id beyond its graph
     with pytest.raises(gpu_lib.TrussError) as ei:
-        gpu_lib.truss_decompose_batched(bad.vtx_off, bad.adj_off, bad.offsets, bad.adj)
+        gpu_lib.truss_decompose_batched(bad.vtx_off, bad.adj_off, bad.offsets, bad.adj, mode=mode)
     assert ei.value.name in ("TRUSS_E_RANGE", "TRUSS_E_NOT_SYMMETRIC", "TRUSS_E_NOT_SIMPLE")
+    # a row out of order, a self-loop, a missing mirror: each rejected
+    for edit, want_name in ((lambda a: a.__setitem__(slice(0, 2), a[0:2][::-1].copy()), "TRUSS_E_NOT_SIMPLE"),
+                            (lambda a: a.__setitem__(0, 0), "TRUSS_E_NOT_SIMPLE"),
+                            (lambda a: a.__setitem__(1, 3), "TRUSS_E_NOT_SYMMETRIC")):
+        t = gg.pack([gg.from_edges(4, [(0, 1), (0, 2), (1, 2), (2, 3)])])
+        edit(t.adj)
+        with pytest.raises(gpu_lib.TrussError) as ei:
+            gpu_lib.truss_decompose_batched(t.vtx_off, t.adj_off, t.offsets, t.adj, mode=mode)
+        assert ei.value.name in (want_name, "TRUSS_E_NOT_SIMPLE", "TRUSS_E_NOT_SYMMETRIC"), (mode, want_name)
     # a graph with no offsets entry at all (it would shift the next graph onto this one's
     # vertices), and graph offsets not starting at 0: rejected in every mode
     ok = gg.pack([gg.from_edges(3, [(0, 1), (1, 2), (0, 2)]), gg.from_edges(3, [(0, 1), (1, 2), (0, 2)])])
     for vo, ao in ((np.array([0, 4, 4, 8], np.int64), np.array([0, 6, 6, 12], np.int64)),
                    (np.array([1, 5, 8], np.int64), ok.adj_off)):
         offs = np.concatenate([ok.offsets, np.zeros(int(vo[-1]) - len(ok.offsets), np.int32)])
-        for seq in (False, True):
+        for mode in ("union", "sequential", "persistent"):
             with pytest.raises(gpu_lib.TrussError) as ei:
-                gpu_lib.truss_decompose_batched(vo, ao, offs, ok.adj, validate=False, sequential=seq)
+                gpu_lib.truss_decompose_batched(vo, ao, offs, ok.adj, validate=False, mode=mode)
             assert ei.value.name == "TRUSS_E_RANGE"
 
 
@@ -251,6 +270,7 @@ def test_full_size_against_stored_oracle(gpu_lib, name):
     dict(force_choice="wide_narrow"),
     dict(compact=False),
     dict(owner_rule=1),
+    dict(force_choice="wave"),
 ])
 def test_full_size_variants_rmat20(gpu_lib, opts):
     """Launch variants and loop drivers at the full R-MAT scale-20 size: every one gives
@@ -278,17 +298,28 @@ def _batch_golden(name):
     return rows
 
 
-@pytest.mark.parametrize("name,mode", [("batch64", "union"), ("batch64", "sequential"), ("batch4096", "union")])
-def test_batch_every_graph_against_stored_oracle(gpu_lib, name, mode):
+@pytest.mark.parametrize("name,mode,variant", [
+    ("batch64", "union", "auto"), ("batch64", "sequential", "auto"), ("batch64", "persistent", "auto"),
+    ("batch64", "union", "wave"), ("batch4096", "union", "auto"), ("batch4096", "persistent", "auto"),
+    ("batch4096", "union", "learned"),
+])
+def test_batch_every_graph_against_stored_oracle(gpu_lib, name, mode, variant):
     """Every graph of the packed batch workloads against the oracle run on that graph alone."""
     import torch
 
     rows = _batch_golden(name)
     b = gg.workload(name, seed=1)
     assert b.num_graphs == len(rows)
-    say("case", name, mode, "graphs", b.num_graphs, "total m", b.total_m)
+    say("case", name, mode, variant, "graphs", b.num_graphs, "total m", b.total_m)
     dev = [torch.from_numpy(x).cuda() for x in (b.vtx_off, b.adj_off, b.offsets, b.adj)]
-    tau = gpu_lib.truss_decompose_batched(*dev, validate=False, sequential=(mode == "sequential")).cpu().numpy()
+    kw = {}
+    if variant == "wave":
+        kw["force_choice"] = "wave"
+    elif variant == "learned":
+        from paper_1707_02000_amd import tuner
+
+        kw.update(variant="learned", mlp_weights=tuner.load_weights())
+    tau = gpu_lib.truss_decompose_batched(*dev, validate=False, mode=mode, **kw).cpu().numpy()
     bad = []
     for g, n, m, t, h in rows:
         s = int(b.adj_off[g]) // 2

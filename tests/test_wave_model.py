@@ -1,0 +1,98 @@
+"""CPU model of the one-wave-per-edge intersection (wave_edge in csrc/psl.h): the
+64-lane chunked merge path -- each lane's entry located among the other row's 64
+register values by a six-step shuffle search, then the chunk pointers advanced by
+ballot counts -- and the bracketed per-lane search for skewed rows, written lane by
+lane.  Both must find exactly the common entries of two sorted rows, each once, at
+their positions in both rows."""
+import numpy as np
+import pytest
+
+W = 64
+BIG = np.iinfo(np.int32).max
+
+
+def wave_rank(lv, s):
+    pos = np.zeros(W, np.int64)
+    step = W // 2
+    while step >= 1:
+        v = lv[pos + step - 1]
+        pos = np.where(v < s, pos + step, pos)
+        step //= 2
+    return pos
+
+
+def merge_model(S, L):
+    a, b = len(S), len(L)
+    found = []
+    i = j = 0
+    steps = 0
+    lane = np.arange(W)
+    while i < a and j < b:
+        steps += 1
+        sv = i + lane < a
+        s = np.where(sv, S[np.minimum(i + lane, a - 1)], BIG)
+        lv = np.where(j + lane < b, L[np.minimum(j + lane, b - 1)], BIG)
+        pos = wave_rank(lv, s)
+        hit = sv & (lv[pos] == s)
+        found += [(i + k, j + int(pos[k])) for k in np.flatnonzero(hit)]
+        s_last, l_last = s[W - 1], lv[W - 1]
+        if s_last <= l_last:
+            j += int(np.count_nonzero(lv <= s_last))
+            i += W
+        else:
+            i += int(np.count_nonzero(sv & (s <= l_last)))
+            j += W
+    return found, steps
+
+
+def search_model(S, L):
+    a = len(S)
+    found = []
+    for i in range(0, a, W):
+        chunk = S[i:i + W]
+        lo = int(np.searchsorted(L, chunk[0], side="left"))
+        hi = int(np.searchsorted(L, chunk[-1], side="right"))
+        for k, s in enumerate(chunk):
+            p = lo + int(np.searchsorted(L[lo:hi], s, side="left"))
+            if p < hi and L[p] == s:
+                found.append((i + k, p))
+    return found
+
+
+def truth(S, L):
+    pos = {int(x): j for j, x in enumerate(L)}
+    return [(i, pos[int(x)]) for i, x in enumerate(S) if int(x) in pos]
+
+
+def rows(rng, a, b, universe, overlap):
+    common = rng.choice(universe, size=min(a, b, int(overlap * min(a, b))), replace=False)
+    rest = np.setdiff1d(np.arange(universe), common)
+    sa = rng.choice(rest, size=a - len(common), replace=False)
+    rest2 = np.setdiff1d(rest, sa)
+    sb = rng.choice(rest2, size=b - len(common), replace=False)
+    return np.sort(np.concatenate([common, sa])).astype(np.int64), np.sort(np.concatenate([common, sb])).astype(np.int64)
+
+
+@pytest.mark.parametrize("a,b", [(1, 1), (1, 64), (63, 64), (64, 64), (65, 64), (64, 65), (100, 700), (700, 100),
+                                 (129, 130), (500, 520), (3, 400), (1000, 1000), (200, 1600), (5, 5000)])
+@pytest.mark.parametrize("overlap", [0.0, 0.3, 1.0])
+def test_merge_and_search_find_every_common_entry_once(a, b, overlap):
+    rng = np.random.default_rng(a * 1000 + b + int(overlap * 7))
+    S, L = rows(rng, a, b, max(4 * (a + b), 64), overlap)
+    want = truth(S, L)
+    got, steps = merge_model(S, L)
+    assert sorted(got) == want and len(set(got)) == len(got)
+    assert steps <= (a + W - 1) // W + (b + W - 1) // W
+    assert sorted(search_model(S, L)) == want
+
+
+def test_interleaved_and_disjoint_ranges():
+    # rows whose values interleave finely, and rows in disjoint ranges (one chunk pointer races ahead)
+    S = np.arange(0, 2000, 2, dtype=np.int64)
+    L = np.arange(1, 2000, 3, dtype=np.int64)
+    assert sorted(merge_model(S, L)[0]) == truth(S, L)
+    S2, L2 = np.arange(0, 300, dtype=np.int64), np.arange(1000, 1300, dtype=np.int64)
+    got, steps = merge_model(S2, L2)
+    assert got == [] and steps <= 10
+    got, _ = merge_model(L2, S2)
+    assert got == []
