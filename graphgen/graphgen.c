@@ -335,11 +335,20 @@ int gg_chunglu(int32_t n, double beta, double target_m, int64_t draws, int32_t n
   double lo = 0.0, hi = (double)n * 4.0;
   double* cdf = (double*)malloc((size_t)n * sizeof(double));
   if (!cdf) return -1;
+  /* The weight sum of the bisection is the sum of two fixed halves, each summed in
+   * index order, whatever the thread count (a parallel reduction's rounding would
+   * depend on it, and the bisection's last steps with it). */
+  const int32_t half = n - n / 2;
   for (int it = 0; it < 60; ++it) {
     double i0 = 0.5 * (lo + hi);
-    double s = 0.0;
-#pragma omp parallel for schedule(static) reduction(+ : s)
-    for (int32_t i = 0; i < n; ++i) s += pow((double)i + i0 + 1.0, -gam);
+    double part[2] = {0.0, 0.0};
+#pragma omp parallel for schedule(static, 1) num_threads(2)
+    for (int h = 0; h < 2; ++h) {
+      double t = 0.0;
+      for (int32_t i = (h ? half : 0); i < (h ? n : half); ++i) t += pow((double)i + i0 + 1.0, -gam);
+      part[h] = t;
+    }
+    double s = part[0] + part[1];
     double ratio = pow(i0 + 1.0, -gam) / s;
     if (ratio > want)
       lo = i0; /* head too heavy: shift further */
