@@ -68,3 +68,24 @@ def test_from_edges_and_pack():
     b = gg.pack([g, gg.from_edges(3, [(0, 2)])])
     assert b.num_graphs == 2 and b.total_m == 4
     assert np.array_equal(b.graph(1).adj, [2, 0])
+
+
+def test_same_graph_at_any_thread_count():
+    # a recipe and seed name one graph whatever OMP_NUM_THREADS is (the Chung-Lu weight
+    # bisection once summed with a parallel reduction, whose rounding followed the
+    # thread count)
+    import os
+    import subprocess
+    import sys
+
+    code = ("import graphgen as gg\n"
+            "for name in ('chunglu18', 'rmat14', 'er4096'):\n"
+            "    print(name, gg.workload(name, seed=1).sha256())\n"
+            "print('batch16', gg.workload('batch16', seed=1).union().sha256())\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    outs = []
+    for t in ("1", "3", "8"):
+        env = dict(os.environ, OMP_NUM_THREADS=t)
+        outs.append(subprocess.run([sys.executable, "-c", code], cwd=root, env=env, capture_output=True, text=True,
+                                   check=True, timeout=300).stdout)
+    assert outs[0] == outs[1] == outs[2]
