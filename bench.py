@@ -34,12 +34,13 @@ WORKLOADS = {
 METRIC = "truss-decomposed edges/s, R-MAT s20/s24; batched+learned vs plain, 1 MI355X"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # Algorithmic bytes of the wide sub-level kernel (one item = one entry of the shorter
-# working row searched in the longer row): the entry's vertex id and edge id (8 B),
-# that edge's state (1 B as a byte; here in its support word) and the longer-row entry
-# the search lands on (4 B);
+# working row searched in the longer row).  Model of the hot-path plan (4 B ids): the
+# shorter-row entry (4 B) and the longer-row entry the search lands on (4 B) per item;
 # per frontier edge: its id (4 B), endpoints (8 B) and four row offsets (32 B).
-BYTES_PER_ITEM = 13
+BYTES_PER_ITEM = 8
 BYTES_PER_FRONTIER_EDGE = 44
+# A fuller model also counts the entry's edge id and that edge's state byte (13 B per item).
+BYTES_PER_ITEM_FULL = 13
 
 
 def sha(a):
@@ -54,25 +55,81 @@ def measured_traffic(workload):
         return None
     fields = dict(l.split(" = ", 1) for l in open(path).read().splitlines() if " = " in l)
     csrc = os.path.join(ROOT, "paper_1707_02000_amd", "csrc")
-    src = "".join(open(os.path.join(csrc, f)).read() for f in ("common.h", "truss.h", "peel.h", "scan.h", "peel.hip"))
+    src = "".join(open(os.path.join(csrc, f)).read()
+                  for f in ("common.h", "truss.h", "peel.h", "scan.h", "psl.h", "peel.hip"))
     if hashlib.sha256(src.encode()).hexdigest()[:16] != fields.get("source_sha256_16", "").strip():
         return None
     return float(fields["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(sample_name="rmat17"):
-    """The CPU oracle (serial bucket peel, one thread) on a bounded sample of the same recipe
-    (R-MAT scale 17: about 20 s of one core)."""
-    import graphgen as gg
-    import oracle
+_CPU_CHILD = r"""
+import json, os, sys, time
+sys.path.insert(0, sys.argv[1])
+cpu = sorted(os.sched_getaffinity(0))[-1]
+os.sched_setaffinity(0, {cpu})  # one host core
+import graphgen as gg
+import oracle
+g = gg.workload(sys.argv[2], seed=1)
+oracle.truss(gg.er(64, mean_degree=4.0, seed=1))  # library loaded before the clock starts
+t0 = time.perf_counter()
+oracle.truss(g)
+print(json.dumps({"m": g.m, "s": time.perf_counter() - t0, "cpu": cpu}))
+"""
 
-    g = gg.workload(sample_name, seed=1)
-    t0 = time.perf_counter()
-    oracle.truss(g)
-    dt = time.perf_counter() - t0
-    return {"value": g.m / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
-            "sample": f"{sample_name}: R-MAT scale {sample_name[4:]}, edge factor 16, same (a,b,c,d) recipe, seed 1 "
-                      f"(m={g.m}); one full serial decomposition, {dt:.1f} s"}
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(sample_name="rmat17"):
+    """The CPU oracle (serial bucket peel) on one pinned host core, in a child process, on a
+    bounded sample of the same recipe (R-MAT scale 17: about 20 s of one core)."""
+    import subprocess
+
+    r = subprocess.run([sys.executable, "-c", _CPU_CHILD, ROOT, sample_name], capture_output=True, text=True,
+                       timeout=600)
+    if r.returncode != 0:
+        raise RuntimeError(f"cpu baseline child failed: {r.stderr[-2000:]}")
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    out = {"value": d["m"] / d["s"], "unit": "edges/s", "cores": 1, "kind": "oracle",
+           "sample": f"{sample_name}: R-MAT scale {sample_name[4:]}, edge factor 16, same (a,b,c,d) recipe, seed 1 "
+                     f"(m={d['m']}); one full serial decomposition on one pinned core, {d['s']:.1f} s",
+           "host_nproc": os.cpu_count(), "host_affinity": len(os.sched_getaffinity(0)), "cpu_model": _cpu_model()}
+    gold = os.path.join(ROOT, "tests", "golden", "rmat20.json")
+    if os.path.exists(gold):  # the stored full-size run, as context (another host, same oracle)
+        rec = json.load(open(gold))
+        out["context_rmat20_oracle"] = {"seconds": rec["oracle_seconds"], "edges_per_s": rec["m"] / rec["oracle_seconds"]}
+    return out
+
+
+def graph_work(g):
+    """Host-side work measures of a CSR: W+ = sum_v d+(v) d-(v) under the (degree, id)
+    orientation (the support walk), W_min = sum over edges of the smaller degree."""
+    deg = np.diff(g.offsets).astype(np.int64)
+    u = np.repeat(np.arange(g.n, dtype=np.int64), deg)
+    v = g.adj.astype(np.int64)
+    up = (deg[u] < deg[v]) | ((deg[u] == deg[v]) & (u < v))  # slot u -> v points up in rank
+    dplus = np.bincount(u[up], minlength=g.n).astype(np.int64)
+    wplus = int((dplus * (deg - dplus)).sum())
+    half = u < v
+    wmin = int(np.minimum(deg[u[half]], deg[v[half]]).sum())
+    return wplus, wmin
+
+
+def model_bytes(g, stats, wplus, wmin):
+    """Algorithmic bytes of one decomposition under the hot-path plan's per-phase models."""
+    m, n, T = g.m, g.n, stats["triangles"]
+    build = 32 * m + 8 * n
+    support = 4 * (m + wplus) + 36 * T
+    scan = 5 * m
+    peel = 4 * wmin + 44 * m
+    return {"build": build, "support": support, "scan": scan, "peel": peel, "total": build + support + scan + peel}
 
 
 def _timed(fn, steps, warmup, torch):
@@ -151,27 +208,38 @@ def extras(pkt, torch, gg, off20, adj20, m20, ms20, steps):
     out["learned_rmat20"] = {"value": m20 / t, "ms_per_step": t * 1e3, "vs_plain": ms20 / (t * 1e3)}
     print(f"bench: learned rmat20 {t * 1e3:.1f} ms", file=sys.stderr, flush=True)
 
-    g = gg.workload("rmat24", seed=1)
-    off = torch.from_numpy(g.offsets).cuda()
-    adj = torch.from_numpy(g.adj).cuda()
-    ws = pkt.Workspace.for_graph(g.n, len(g.adj))
-    o = torch.empty(g.m, dtype=torch.int32, device="cuda")
-    ref, st = pkt.truss_decompose(off, adj, validate=True, workspace=ws, out=o, return_stats=True)
-    ref = ref.clone()
-    tp = _timed(lambda: pkt.truss_decompose(off, adj, validate=False, workspace=ws, out=o), 2, 0, torch)
-    tl = _timed(lambda: pkt.truss_decompose(off, adj, validate=False, workspace=ws, out=o, variant="learned",
-                                            mlp_weights=W), 2, 0, torch)
-    same = bool(torch.equal(o, ref))
-    out["rmat24"] = {"m": g.m, "value": g.m / tp, "ms_per_step": tp * 1e3, "t_max": st["t_max"],
-                     "levels": st["levels"], "sublevels": st["sublevels"],
+    for name in ("rmat24", "chunglu23", "er4096"):
+        g = gg.workload(name, seed=1)
+        off = torch.from_numpy(g.offsets).cuda()
+        adj = torch.from_numpy(g.adj).cuda()
+        ws = pkt.Workspace.for_graph(g.n, len(g.adj))
+        o = torch.empty(max(g.m, 1), dtype=torch.int32, device="cuda")
+        ref, st = pkt.truss_decompose(off, adj, validate=True, workspace=ws, out=o, return_stats=True)
+        ref = ref.clone()
+        reps = 2 if g.m > 5e7 else 5
+        tp = _timed(lambda: pkt.truss_decompose(off, adj, validate=False, workspace=ws, out=o), reps, 1, torch)
+        tl = _timed(lambda: pkt.truss_decompose(off, adj, validate=False, workspace=ws, out=o, variant="learned",
+                                                mlp_weights=W), reps, 1, torch)
+        same = bool(torch.equal(o[:g.m], ref[:g.m]))
+        gold = os.path.join(ROOT, "tests", "golden", f"{name}.json")
+        parity = None
+        if os.path.exists(gold):
+            rec = json.load(open(gold))
+            parity = rec["csr_sha256"] == g.sha256() and rec["trussness_sha256"] == sha(ref[:g.m].cpu().numpy())
+        out[name] = {"m": g.m, "value": g.m / tp, "ms_per_step": tp * 1e3, "t_max": st["t_max"],
+                     "levels": st["levels"], "sublevels": st["sublevels"], "parity_vs_oracle": parity,
                      "learned_value": g.m / tl, "learned_vs_plain": tp / tl, "learned_bit_identical": same}
-    print(f"bench: rmat24 plain {tp * 1e3:.0f} ms learned {tl * 1e3:.0f} ms", file=sys.stderr, flush=True)
-    del off, adj, ws, o, ref
-    torch.cuda.empty_cache()
+        print(f"bench: {name} plain {tp * 1e3:.1f} ms learned {tl * 1e3:.1f} ms parity {parity}", file=sys.stderr,
+              flush=True)
+        del off, adj, ws, o, ref
+        torch.cuda.empty_cache()
 
     b = gg.workload("batch4096", seed=1)
     args_b = [torch.from_numpy(x).cuda() for x in (b.vtx_off, b.adj_off, b.offsets, b.adj)]
     tb = _timed(lambda: pkt.truss_decompose_batched(*args_b, validate=False), 2, 1, torch)
+    tbl = _timed(lambda: pkt.truss_decompose_batched(*args_b, validate=False, variant="learned", mlp_weights=W),
+                 2, 1, torch)
+    tbp = _timed(lambda: pkt.truss_decompose_batched(*args_b, validate=False, mode="persistent"), 2, 1, torch)
     G = 256  # the sequential comparison on the first graphs (one after another is slow)
     sub = [torch.from_numpy(x).cuda() for x in
            (b.vtx_off[:G + 1], b.adj_off[:G + 1], b.offsets[:int(b.vtx_off[G])], b.adj[:int(b.adj_off[G])])]
@@ -179,10 +247,12 @@ def extras(pkt, torch, gg, off20, adj20, m20, ms20, steps):
     tu = _timed(lambda: pkt.truss_decompose_batched(*sub, validate=False), 2, 1, torch)
     tsq = _timed(lambda: pkt.truss_decompose_batched(*sub, validate=False, sequential=True), 1, 1, torch)
     out["batch4096"] = {"graphs": b.num_graphs, "m": b.total_m, "value": b.total_m / tb, "ms_per_step": tb * 1e3,
+                        "learned_value": b.total_m / tbl, "learned_vs_plain": tb / tbl,
+                        "persistent_value": b.total_m / tbp, "persistent_vs_union": tb / tbp,
                         "first_256": {"m": m_sub, "union_value": m_sub / tu, "sequential_value": m_sub / tsq,
                                       "union_vs_sequential": tsq / tu}}
-    print(f"bench: batch4096 {tb * 1e3:.0f} ms; first 256 union {tu * 1e3:.1f} ms sequential {tsq * 1e3:.1f} ms",
-          file=sys.stderr, flush=True)
+    print(f"bench: batch4096 union {tb * 1e3:.0f} ms, learned {tbl * 1e3:.0f} ms, persistent {tbp * 1e3:.0f} ms; "
+          f"first 256 union {tu * 1e3:.1f} ms sequential {tsq * 1e3:.1f} ms", file=sys.stderr, flush=True)
     return out
 
 
@@ -273,13 +343,26 @@ def main():
     roofline = None
     if launches and dom_ms > 0:
         achieved = alg_bytes / launches / (dom_ms / launches / 1e3) / 1e9
+        full = (BYTES_PER_ITEM_FULL * items + BYTES_PER_FRONTIER_EDGE * frontier) / (dom_ms / 1e3) / 1e9
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload),
                     "kernel": "k_psl_bsearch", "launches_per_step": launches / args.steps,
                     "avg_launch_us": dom_ms / launches * 1e3,
                     "alg_bytes_per_launch": alg_bytes / launches,
-                    "model": f"{BYTES_PER_ITEM} B per shorter-row entry searched + "
-                             f"{BYTES_PER_FRONTIER_EDGE} B per frontier edge"}
+                    "model": f"{BYTES_PER_ITEM} B per shorter-row entry searched (the entry and the longer-row "
+                             f"entry its search lands on) + {BYTES_PER_FRONTIER_EDGE} B per frontier edge",
+                    "frac_full_model": full / HBM_PEAK_GBS,
+                    "full_model": f"{BYTES_PER_ITEM_FULL} B per entry (also its edge id and state byte)"}
+    # the whole step and the support kernel against the same roofline, by the per-phase models
+    wplus, wmin = graph_work(g)
+    mb = model_bytes(g, st0, wplus, wmin)
+    step_frac = mb["total"] / (ms / 1e3) / 1e9 / HBM_PEAK_GBS
+    sup_ms = phases["ms_support"]
+    support_roofline = {"kernel": "k_support", "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+                        "alg_bytes": mb["support"], "ms": sup_ms,
+                        "achieved": mb["support"] / (sup_ms / 1e3) / 1e9 if sup_ms > 0 else None,
+                        "frac": mb["support"] / (sup_ms / 1e3) / 1e9 / HBM_PEAK_GBS if sup_ms > 0 else None,
+                        "model": "4 (m + W+) B of rows + 36 B per triangle", "W_plus": wplus}
     line = {
         "metric": METRIC,
         "value": value,
@@ -302,6 +385,10 @@ def main():
         "sublevels": st0["sublevels"],
         "phases_ms": phases,
         "roofline": roofline,
+        "whole_step": {"alg_bytes": mb, "frac": step_frac, "W_min": wmin,
+                       "model": "build 32m + 8n; support 4(m + W+) + 36 B/triangle; scan 5 B/edge; "
+                                "peel 4 W_min + 44 B per frontier edge"},
+        "support_roofline": support_roofline,
         "cpu_baseline": None,
     }
     if not args.no_extras and args.workload == "rmat20":

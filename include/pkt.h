@@ -139,10 +139,10 @@ typedef struct {
   int32_t profile;           /* 1 = time every launch of the wide sub-level kernel with events
                                 (truss_stats.wide_ms) */
   int32_t batch_mode;        /* truss_decompose_batched: 0 = all graphs at once as one disjoint
-                                union through one level loop; 1 = one graph after another
-                                through the single-graph path (a comparison point); 2 = one
-                                persistent launch, one workgroup per graph from a queue ordered
-                                by decreasing edge count (default) */
+                                union through one level loop (default); 1 = one graph after
+                                another through the single-graph path (a comparison point);
+                                2 = one persistent launch, one workgroup per graph from a queue
+                                ordered by decreasing edge count */
   int32_t force_choice;      /* truss_choice for TRUSS_VARIANT_FIXED */
   int32_t single_round;      /* 1 = every launch sequence runs exactly one frontier round (no
                                 continuation of tiny rounds inside the fused launch); for
@@ -150,7 +150,11 @@ typedef struct {
   int32_t* peel_round;       /* device, int32[m], or NULL: receives for every edge the index of the
                                 frontier round that processed it (a peeling order: rounds run in
                                 level order, so a lower trussness never gets a later round) */
-  int32_t reserved[8];       /* zero (room for later options without a layout change) */
+  int32_t multi_round;       /* 1 = with device_loop 0 or 3, consecutive fused rounds run in one
+                                cooperative launch of 64 workgroups that meet at a grid barrier
+                                between rounds (measured slower than one launch per round on
+                                this GPU; default 0) */
+  int32_t reserved[7];       /* zero (room for later options without a layout change) */
 } truss_options;
 
 typedef struct {

@@ -64,7 +64,8 @@ class Options(ctypes.Structure):
         ("force_choice", ctypes.c_int32),
         ("single_round", ctypes.c_int32),
         ("peel_round", ctypes.c_void_p),
-        ("reserved", ctypes.c_int32 * 8),
+        ("multi_round", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 7),
     ]
 
 
@@ -203,7 +204,7 @@ def default_options() -> Options:
 
 def make_options(variant="auto", device_loop="pipelined", validate=True, owner_rule=0, compact=True,
                  steps_per_sync=0, mlp_weights=None, profile=False, force_choice=None,
-                 single_round=False) -> Options:
+                 single_round=False, multi_round=False) -> Options:
     o = default_options()
     o.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
     o.device_loop = loop_mode(device_loop)
@@ -217,6 +218,7 @@ def make_options(variant="auto", device_loop="pipelined", validate=True, owner_r
         o.variant = VARIANTS["fixed"]
         o.force_choice = CHOICES.index(force_choice) if isinstance(force_choice, str) else int(force_choice)
     o.single_round = int(bool(single_round))
+    o.multi_round = int(bool(multi_round))
     return o
 
 
@@ -284,7 +286,7 @@ class Workspace:
 def truss_decompose(offsets, adj, *, variant="auto", device_loop="pipelined", validate=True, owner_rule=0,
                     compact=True, steps_per_sync=0, mlp_weights=None, stream=None, workspace=None,
                     out=None, return_stats=False, trace_capacity=0, profile=False, force_choice=None,
-                    single_round=False, return_rounds=False):
+                    single_round=False, return_rounds=False, multi_round=False):
     """Trussness (int32, >= 2) of every edge of a simple undirected CSR graph, on the GPU.
 
     offsets: int64 (or int32) [n+1]; adj: int32 [2m]; numpy arrays (copied to the GPU) or
@@ -303,7 +305,7 @@ def truss_decompose(offsets, adj, *, variant="auto", device_loop="pipelined", va
     two_m = adj_t.numel()
     m = two_m // 2
     opt = make_options(variant, device_loop, validate, owner_rule, compact, steps_per_sync, mlp_weights, profile,
-                       force_choice, single_round)
+                       force_choice, single_round, multi_round)
     if workspace is None:
         nb = workspace_bytes(n, two_m, opt) + (8 * (n + 1) + 256 if off32 else 0)
         _buf, wptr = alloc_workspace(nb)
@@ -516,13 +518,13 @@ BATCH_MODES = {"union": 0, "sequential": 1, "persistent": 2}  # truss_options.ba
 
 
 def truss_decompose_batched(vtx_off, adj_off, offsets_packed, adj_packed, *, variant="auto", validate=True,
-                            mode="persistent", sequential=False, stream=None, workspace=None, out=None,
+                            mode="union", sequential=False, stream=None, workspace=None, out=None,
                             return_stats=False, device_loop="pipelined", mlp_weights=None, force_choice=None):
     """Trussness of many packed graphs (layout of include/pkt.h); int32 [sum m_g] CUDA tensor.
 
-    mode: "persistent" (one launch, a workgroup per graph), "union" (one level loop over the
-    disjoint union) or "sequential" (one graph after another); sequential=True is the same
-    as mode="sequential"."""
+    mode: "union" (one level loop over the disjoint union, the default), "persistent" (one
+    launch, a workgroup per graph) or "sequential" (one graph after another);
+    sequential=True is the same as mode="sequential"."""
     torch = _torch()
     lib = load()
     vo = _dev(vtx_off, torch.int64, torch)

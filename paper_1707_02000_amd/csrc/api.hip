@@ -214,7 +214,7 @@ void truss_default_options(truss_options* opt) {
   opt->mlp_weights = nullptr;
   opt->trace = nullptr;
   opt->profile = 0;
-  opt->batch_mode = 2;
+  opt->batch_mode = 0;
   opt->force_choice = 0;
   opt->single_round = 0;
 }

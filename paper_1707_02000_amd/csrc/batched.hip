@@ -1,13 +1,13 @@
 // Batched decomposition of many independent graphs, three ways (truss_options::
 // batch_mode):
-//   2 (default) one persistent launch, every workgroup decomposing whole graphs
-//     taken from a queue ordered by decreasing size (persist.hip);
-//   0 the disjoint union: trussness is a property of each connected component, and
+//   0 (default) the disjoint union: trussness is a property of each connected component, and
 //     the edge order of the output (row-major, per graph, graphs back to back) is
 //     exactly the edge order of the disjoint union of the graphs with vertex ids
 //     shifted by the graph's vertex base, so the batch is decomposed as one union
 //     graph: one level loop, one sequence of launches for every graph at once;
-//   1 one graph after another through the single-graph path (a comparison point).
+//   1 one graph after another through the single-graph path (a comparison point);
+//   2 one persistent launch, every workgroup decomposing whole graphs taken from a
+//     queue ordered by decreasing size (persist.hip).
 #include <string.h>
 
 #include <vector>

@@ -94,6 +94,7 @@ struct PeelArgs {
   int single_round;
   const float* mlp;  // cost-model weights (TRUSS_VARIANT_LEARNED) or NULL
   int want_features; // frontier features: 0 never, 1 learned policy (large frontiers), 2 every decision (tracing)
+  int multi;         // fused rounds run as one cooperative multi-round launch (k_psl_multi)
 };
 
 __device__ __forceinline__ i32* cur_of(const PeelArgs& a, int sel) { return a.F[sel]; }

@@ -197,6 +197,7 @@ __device__ void decide(const PeelArgs& a, float* sx, float* sy, float* ha, float
     }
     ctl->choice = c;
     ctl->chosen[c] += 1;
+    for (int k = 0; k < 3; ++k) ctl->mcnt[k] = 0;  // counters of a multi-round launch
     ctl->variant = (policy == TRUSS_VARIANT_MERGE || c == TRUSS_CHOICE_WIDE_GALLOP) ? TRUSS_VARIANT_MERGE
                                                                                      : TRUSS_VARIANT_BSEARCH;
     for (int i = 0; i < 8; ++i) ctl->feat[i] = i < TRUSS_NUM_FEATURES ? sx[i] : 0.f;
@@ -472,11 +473,13 @@ struct BlockAppend {
 };
 
 // Items [base, total) with the given stride, pairs located through LDS P (and
-// the edges' rows from LDS when er is given); appends through ba when given.
+// the edges' rows from LDS when er is given); appends through ba when given, and
+// to `next` with the round's counter (Ctl::nnext unless given).
 template <int NT>
 __device__ void lds_items(const PeelArgs& a, const Csr& c, const i32* curr, i32 nc, i32 l, i32 r, int variant,
                           const i64* P, i64 total, i64 base, i64 stride, i32* next, const EdgeRows* er = nullptr,
-                          BlockAppend* ba = nullptr) {
+                          BlockAppend* ba = nullptr, i32* counter = nullptr) {
+  if (counter == nullptr) counter = &a.ctl->nnext;
   for (i64 b = base; b < total; b += stride) {
     const i64 g = b + threadIdx.x;
     i32 x0 = -1, x1 = -1;
@@ -488,15 +491,15 @@ __device__ void lds_items(const PeelArgs& a, const Csr& c, const i32* curr, i32 
         rw.slen = er->slen[i];
         rw.lb = er->lb[i];
         rw.le = rw.lb + er->L[i];
-        psl_item_rows(a, c, er->e1[i], rw, g - P[i], l, r, variant, x0, x1, next, &a.ctl->nnext);
+        psl_item_rows(a, c, er->e1[i], rw, g - P[i], l, r, variant, x0, x1, next, counter);
       } else {
-        psl_item(a, c, curr[i], g - P[i], l, r, variant, x0, x1, next, &a.ctl->nnext);
+        psl_item(a, c, curr[i], g - P[i], l, r, variant, x0, x1, next, counter);
       }
     }
     if (ba)
-      ba->add(x0, x1, next, &a.ctl->nnext);
+      ba->add(x0, x1, next, counter);
     else
-      append_next(x0, x1, next, &a.ctl->nnext);
+      append_next(x0, x1, next, counter);
   }
 }
 
@@ -815,6 +818,102 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_psl_small(PeelArgs a) {
   lds_items<SMALL_THREADS>(a, c, curr, nc, l, r, v.variant, P, total, (i64)blockIdx.x * SMALL_THREADS,
                            (i64)nblk * SMALL_THREADS, next, &er, &ba);
   ba.flush(next, &ctl->nnext);
+}
+
+// Grid barrier of a cooperative launch (every block resident): release this
+// block's writes, arrive, wait for the generation to move on, acquire everyone
+// else's.  The wait is bounded: after MULTI_SPIN polls the block gives up and sets
+// Ctl::bar_timeout, which the host turns into an error, so a kernel can never spin
+// for good.  Every thread of every block calls it; returns false after a timeout.
+#define MULTI_SPIN (1 << 22)
+__device__ __forceinline__ bool grid_barrier(Ctl* ctl, u32 nblk, int* sflag) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const u32 g = __hip_atomic_load(&ctl->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int ok = 1;
+    if (atomicAdd(&ctl->bar_count, 1u) == nblk - 1) {
+      __hip_atomic_store(&ctl->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&ctl->bar_gen, g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      int spins = 0;
+      while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > MULTI_SPIN) {
+          atomicExch(&ctl->bar_timeout, 1);
+          ok = 0;
+          break;
+        }
+      }
+    }
+    __threadfence();
+    *sflag = ok && atomic_load_relaxed(&ctl->bar_timeout) == 0;
+  }
+  __syncthreads();
+  return *sflag != 0;
+}
+
+// Consecutive rounds of small frontiers (at most SMALL_FRONTIER edges, launch choice
+// TRUSS_CHOICE_FUSED) in one cooperative launch of MULTI_BLOCKS blocks: every round
+// runs as in k_psl_small on the blocks' share of the items, then all blocks meet at
+// a grid barrier instead of a kernel boundary.  Every block reads the next
+// frontier's size after the barrier and keeps its own copy of the loop state; the
+// next-frontier counter of round r is Ctl::mcnt[r % 3] (zeroed by the decision
+// before the launch, and by block 0 a round ahead: round r + 1's counter was last
+// read before barrier r - 1).  The loop stops when the next frontier is empty (the
+// level is done) or too large for a fused round; block 0 then writes the loop state
+// to the control block and k_decide picks the next launch.
+#ifndef MULTI_BLOCKS
+#define MULTI_BLOCKS 64
+#endif
+__global__ __launch_bounds__(SMALL_THREADS) void k_psl_multi(PeelArgs a) {
+  Ctl* ctl = a.ctl;
+  __shared__ i64 P[SMALL_FRONTIER + 1];
+  __shared__ i64 tmp[SMALL_THREADS / PKT_WAVE];
+  __shared__ EdgeRows er;
+  __shared__ CtlView v;
+  __shared__ BlockAppend ba;
+  __shared__ int sflag;
+  load_view(ctl, &v);  // every block sees the same state: nothing writes it before the end
+  if (v.done || v.ncurr == 0 || v.ncurr > SMALL_FRONTIER || v.choice != TRUSS_CHOICE_FUSED) return;
+  const u32 nblk = gridDim.x;
+  const i32 l = v.level;
+  const Csr c = a.csr.pick(v.csel);
+  i32 nc = v.ncurr, sel = v.sel, r = v.r, nprev = v.nprev, rounds = 0, processed = 0;
+  for (;;) {
+    const i32* curr = cur_of(a, sel);
+    i32* next = next_of(a, sel);
+    i32* counter = &ctl->mcnt[r % 3];
+    if (threadIdx.x == 0) ba.n = 0;  // visible after the prefix's barrier
+    mark_prev(a, sel, r, nprev, (i64)blockIdx.x * SMALL_THREADS + threadIdx.x, (i64)nblk * SMALL_THREADS);
+    const i64 total = lds_work_prefix<SMALL_THREADS>(a, c, curr, nc, l, v.variant, P, tmp, &er);
+    lds_items<SMALL_THREADS>(a, c, curr, nc, l, r, v.variant, P, total, (i64)blockIdx.x * SMALL_THREADS,
+                             (i64)nblk * SMALL_THREADS, next, &er, &ba, counter);
+    ba.flush(next, counter);
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->mcnt[(r + 1) % 3] = 0;
+    const bool ok = grid_barrier(ctl, nblk, &sflag);
+    const i32 nn = atomic_load_relaxed(counter);
+    processed += nc;
+    nprev = nc;
+    sel = sel == 2 ? 0 : sel + 1;
+    ++r;
+    ++rounds;
+    nc = nn;
+    if (!ok || nn == 0 || nn > SMALL_FRONTIER) break;
+    __syncthreads();  // ba and the LDS prefix are rewritten by the next round
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl->processed += processed;
+    ctl->ncurr = nc;
+    ctl->nnext = 0;
+    ctl->nprev = nprev;
+    ctl->sel = sel;
+    ctl->sublevels += rounds;
+    ctl->chosen[TRUSS_CHOICE_FUSED] += rounds - 1;
+    if (nc == 0) ctl->level += 1;
+    ctl->choice = CHOICE_NONE;  // k_decide picks the next launch
+    ctl->round_done = 0;
+  }
 }
 
 // Work of frontier edge i for the device-wide scan (wide rounds above level 0).
@@ -1138,6 +1237,14 @@ struct KernelClock {
 #define PIPE_ALONE 0  // 1: the continuation with the pipelined loop too (tuning builds)
 #endif
 
+// Cooperative launch of the multi-round kernel: every block resident at once, as its
+// grid barrier needs.
+static truss_status launch_multi(PeelArgs a, hipStream_t s) {
+  void* args[] = {&a};
+  PKT_HIP(hipLaunchCooperativeKernel((const void*)k_psl_multi, dim3(MULTI_BLOCKS), dim3(SMALL_THREADS), args, 0, s));
+  return TRUSS_OK;
+}
+
 PeelArgs peel_args(const Work& w, const truss_options& opt) {
   PeelArgs a;
   a.ctl = w.ctl;
@@ -1160,6 +1267,11 @@ PeelArgs peel_args(const Work& w, const truss_options& opt) {
   a.single_round = opt.single_round != 0;
   a.mlp = opt.mlp_weights;
   a.want_features = opt.trace != nullptr ? 2 : (opt.variant == TRUSS_VARIANT_LEARNED ? 1 : 0);
+  // consecutive fused rounds in one cooperative launch (truss_options::multi_round), for
+  // the host-driven and pipelined loops (the device-driven steps and captured graphs
+  // keep one launch per round; tracing and single_round time every round on its own)
+  a.multi = opt.multi_round != 0 && !opt.single_round && opt.trace == nullptr &&
+            (opt.device_loop == 0 || opt.device_loop == 3);
   return a;
 }
 
@@ -1193,8 +1305,13 @@ static truss_status launch_round(const Work& w, const PeelArgs& a, const Ctl& hc
     hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a, (i64)0, 0);
   } else if (hc.choice == TRUSS_CHOICE_FUSED || hc.choice == TRUSS_CHOICE_FUSED_NARROW) {
     *kind = 1;
-    const int blocks = hc.choice == TRUSS_CHOICE_FUSED ? FUSED_BLOCKS : FUSED_NARROW_BLOCKS;
-    hipLaunchKernelGGL(k_psl_small, dim3(blocks), dim3(SMALL_THREADS), 0, s, a);
+    if (a.multi && hc.choice == TRUSS_CHOICE_FUSED) {
+      truss_status st = launch_multi(a, s);
+      if (st) return st;
+    } else {
+      const int blocks = hc.choice == TRUSS_CHOICE_FUSED ? FUSED_BLOCKS : FUSED_NARROW_BLOCKS;
+      hipLaunchKernelGGL(k_psl_small, dim3(blocks), dim3(SMALL_THREADS), 0, s, a);
+    }
     hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a, (i64)0, 0);
   } else if (hc.choice == TRUSS_CHOICE_WAVE) {
     *kind = 3;
@@ -1272,8 +1389,13 @@ static truss_status enqueue_seq(const Work& w, const PeelArgs& a, int kind, int 
     hipLaunchKernelGGL(k_scan_write, dim3(G), dim3(PKT_BLOCK), 0, s, a, (const i64*)w.partial,
                        (const u32*)scan_bits(w));
   } else if (kind == SEQ_FUSED) {
-    const int blocks = choice == TRUSS_CHOICE_FUSED_NARROW ? FUSED_NARROW_BLOCKS : FUSED_BLOCKS;
-    hipLaunchKernelGGL(k_psl_small, dim3(blocks), dim3(SMALL_THREADS), 0, s, a);
+    if (a.multi && choice == TRUSS_CHOICE_FUSED) {
+      truss_status st = launch_multi(a, s);
+      if (st) return st;
+    } else {
+      const int blocks = choice == TRUSS_CHOICE_FUSED_NARROW ? FUSED_NARROW_BLOCKS : FUSED_BLOCKS;
+      hipLaunchKernelGGL(k_psl_small, dim3(blocks), dim3(SMALL_THREADS), 0, s, a);
+    }
   } else if (kind == SEQ_WAVE) {
     hipLaunchKernelGGL(k_psl_wave, dim3(WIDE_BLOCKS), dim3(WIDE_THREADS), 0, s, a);
   } else if (kind == SEQ_WIDE) {
@@ -1461,7 +1583,13 @@ truss_status run_single(const Work& w, const truss_options& opt, truss_stats* st
     int nfl = 0;
     LoopState cur = state_of(hc, w.m);
     int after_scan = SEQ_WIDE;  // kind of the round that followed the last level scan
-    auto guess_after = [&](int kind) { return kind == SEQ_SCAN ? after_scan : (kind == SEQ_DECIDE ? SEQ_WIDE : kind); };
+    // after a multi-round launch the level is usually done: a level scan follows
+    auto guess_after = [&](int kind) {
+      if (kind == SEQ_SCAN) return after_scan;
+      if (kind == SEQ_DECIDE) return (int)SEQ_WIDE;
+      if (kind == SEQ_FUSED && a.multi) return (int)SEQ_SCAN;
+      return kind;
+    };
     // Tops the pipeline up to `depth` sequences.  The sequences in flight are
     // replayed against the last state seen: one of the state's kind does its
     // round (what follows is guessed: the same kind again, or after a level scan
@@ -1597,6 +1725,10 @@ truss_status run_single(const Work& w, const truss_options& opt, truss_stats* st
   tm.mark();  // 5
   st = read_ctl(w, &hc, s);
   if (st) return st;
+  if (hc.bar_timeout) {
+    set_error("a grid barrier of the multi-round launch timed out");
+    return TRUSS_E_INTERNAL;
+  }
   if (hc.processed != w.m) {
     set_error("peeling ended with %lld of %lld edges processed", (long long)hc.processed, (long long)w.m);
     return TRUSS_E_INTERNAL;

@@ -7,10 +7,11 @@
 // edge, the randomly read and atomically updated array) in LDS.  Graphs above
 // PB_MAX_EDGES are left to the single-graph path after the launch.
 //
-// Inside a workgroup every frontier edge and every support count is taken by one
-// wave (wave_intersect: the two rows merged in 64-entry chunks, or the shorter
-// row's entries searched in the longer one), from a counter in LDS, so a wave
-// that finishes early takes the next edge.
+// Inside a workgroup the support counts and every round work on chunks of up to
+// PB_CH edges: the chunk's rows and the exclusive prefix of its shorter-row
+// lengths go to LDS, and every lane takes one entry of a shorter row (an item),
+// finds its edge in the prefix and binary-searches the entry in the longer row --
+// the rounds' load spreads over the lanes whatever the degrees.
 #include <limits.h>
 #include <string.h>
 
@@ -22,12 +23,14 @@
 #define PB_THREADS 512
 #define PB_WAVES (PB_THREADS / PKT_WAVE)
 #ifndef PB_LDS_EDGES
-#define PB_LDS_EDGES 12288  // support words in LDS for graphs up to this many edges (48 KB)
+#define PB_LDS_EDGES 8192  // support words in LDS for graphs up to this many edges (32 KB)
 #endif
+#define PB_CH 1024  // edges per chunk of items (rows and work prefix in LDS)
 #define PB_MAX_EDGES (1 << 22)  // larger graphs go through the single-graph path
-#ifndef PB_WG_PER_CU
-#define PB_WG_PER_CU 2  // workgroups per compute unit (100 VGPRs: 4 waves per SIMD)
+#ifndef PB_MIN_WAVES
+#define PB_MIN_WAVES 4  // waves per SIMD the kernel's registers must allow (4: no spills)
 #endif
+#define PB_WG_PER_CU (PB_MIN_WAVES / 2)  // workgroups per compute unit (8 waves each, 4 SIMDs)
 
 namespace pkt {
 truss_status run_single(const Work& w, const truss_options& opt, truss_stats* stats, i32* trussness,
@@ -66,8 +69,61 @@ struct PbArgs {
 
 struct PbShared {
   i64 tmp[PB_WAVES];
-  i32 g, take, n0, n1, mn, bad;
+  i32 P[PB_CH + 1];                      // exclusive prefix of the chunk's shorter-row lengths
+  i32 sb[PB_CH], lb[PB_CH], ll[PB_CH];   // shorter-row start, longer-row start and length
+  i32 e1[PB_CH];                         // the chunk's edges
+  i32 g, n0, n1, mn, bad;
 };
+
+// Rows of the edges list[i] (i < cnt <= PB_CH; list NULL: edges first + i) into LDS,
+// with the exclusive prefix of their shorter-row lengths (no items with nowork).
+// Returns the chunk's items.  Every thread calls it.
+__device__ i32 pb_chunk(const i32* __restrict__ O, const int2* __restrict__ EL, const i32* __restrict__ list,
+                        i32 first, i32 cnt, bool nowork, PbShared& sh) {
+  constexpr int PER = PB_CH / PB_THREADS;
+  i32 w[PER];
+  i64 sum = 0;
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const i32 i = threadIdx.x * PER + k;
+    w[k] = 0;
+    if (i < cnt) {
+      const i32 e = list ? list[i] : first + i;
+      const int2 uv = EL[e];
+      const i32 ub = O[uv.x], ue = O[uv.x + 1], vb = O[uv.y], ve = O[uv.y + 1];
+      const bool us = ue - ub <= ve - vb;
+      sh.e1[i] = e;
+      sh.sb[i] = us ? ub : vb;
+      sh.lb[i] = us ? vb : ub;
+      sh.ll[i] = us ? ve - vb : ue - ub;
+      w[k] = nowork ? 0 : (us ? ue - ub : ve - vb);
+    }
+    sum += w[k];
+  }
+  i64 tot;
+  i64 run = block_excl_scan_i64<PB_THREADS>(sum, sh.tmp, &tot);
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const i32 i = threadIdx.x * PER + k;
+    if (i < cnt) sh.P[i] = (i32)run;
+    run += w[k];
+  }
+  if (threadIdx.x == 0) sh.P[cnt] = (i32)tot;
+  __syncthreads();
+  return (i32)tot;
+}
+
+// Item g of the chunk (g < items): its edge k, and the slots of its shorter-row
+// entry and of the same vertex in the longer row (jl = -1 if absent).
+__device__ __forceinline__ void pb_item(const i32* __restrict__ A, const PbShared& sh, i32 cnt, i32 g, i32& k,
+                                        i32& js, i32& jl) {
+  k = (i32)upper_bound_dev(sh.P, (i32)0, cnt + 1, g) - 1;
+  js = sh.sb[k] + (g - sh.P[k]);
+  const i32 w = A[js];
+  const i32 lo = sh.lb[k], hi = lo + sh.ll[k];
+  const i32 q = lower_bound_dev(A, lo, hi, w);
+  jl = (q < hi && A[q] == w) ? q : -1;
+}
 
 // Appends of one round to the next frontier: per wave, one LDS reservation.
 struct PbAppend {
@@ -87,25 +143,6 @@ struct PbAppend {
     add1(x1);
   }
 };
-
-// Shorter / longer row of edge (u, v) in a graph with int32 offsets O.
-__device__ __forceinline__ Rows rows32(const i32* __restrict__ O, int2 uv) {
-  const i64 ub = O[uv.x], ue = O[uv.x + 1], vb = O[uv.y], ve = O[uv.y + 1];
-  Rows r;
-  if (ue - ub <= ve - vb) {
-    r.sb = ub; r.slen = ue - ub; r.lb = vb; r.le = ve;
-  } else {
-    r.sb = vb; r.slen = ve - vb; r.lb = ub; r.le = ue;
-  }
-  return r;
-}
-
-// Next item of a dynamic loop over [0, count) for the calling wave (LDS counter).
-__device__ __forceinline__ i32 wave_take(i32* take) {
-  i32 i = 0;
-  if (lane_id() == 0) i = atomicAdd(take, 1);
-  return __shfl(i, 0);
-}
 
 // Ends a checking phase: every thread's flag is in, the graph is dropped if any
 // check failed (the error bits and the graph index are recorded).  Uniform.
@@ -205,26 +242,36 @@ __device__ void pb_graph(const PbArgs& p, i32 g, PbShared& sh, i32* lsw) {
   }
   if (phase_failed(sh, p, g, bits)) return;
 
-  // ---- support: one wave per edge
-  if (tid == 0) sh.take = 0;
+  // ---- support: per chunk of edges, one lane per shorter-row entry; the hits of the
+  // lanes that share an edge are summed in the wave and added to its word at once
+  for (i32 e = tid; e < m; e += PB_THREADS) SW[e] = 0;
   __syncthreads();
   i64 tri3 = 0;
-  for (;;) {
-    const i32 e = wave_take(&sh.take);
-    if (e >= m) break;
-    const i32 s = wave_common(A, rows32(O, EL[e]));
-    if (lane == 0) {
-      SW[e] = sw_make(s, ST_ALIVE);
-      tri3 += s;
+  for (i32 c0 = 0; c0 < m; c0 += PB_CH) {
+    const i32 cnt = min(PB_CH, m - c0);
+    const i32 items = pb_chunk(O, EL, nullptr, c0, cnt, false, sh);
+    for (i32 base = 0; base < items; base += PB_THREADS) {
+      const i32 gi = base + tid;
+      i32 k = -1, js, jl = -1;
+      if (gi < items) pb_item(A, sh, cnt, gi, k, js, jl);
+      u64 todo = __ballot(k >= 0);
+      const u64 hits = __ballot(jl >= 0);
+      while (todo) {  // lanes' edges are non-decreasing: a few segments per wave
+        const int lead = __ffsll((unsigned long long)todo) - 1;
+        const i32 kl = __shfl(k, lead);
+        const u64 same = __ballot(k == kl);
+        const i32 c = (i32)__popcll(hits & same);
+        if (lane == lead && c) {
+          atomicAdd(&SW[c0 + kl], c << SW_SHIFT);  // state bits stay ST_ALIVE
+          tri3 += c;
+        }
+        todo &= ~same;
+      }
     }
+    __syncthreads();  // the chunk's LDS is rewritten by the next one
   }
-  __syncthreads();
 
   // ---- level loop
-  Csr c;
-  c.off = nullptr;  // rows come from the int32 offsets
-  c.adj = A;
-  c.eid = EID;
   i32* AL = p.al0 + e0;
   i32* ALn = p.al1 + e0;
   i32* FA = p.fa + e0;
@@ -300,18 +347,24 @@ __device__ void pb_graph(const PbArgs& p, i32 g, PbShared& sh, i32* lsw) {
     // rounds of level l until no edge reaches it
     while (nf > 0 && guard <= guard_max) {
       ++guard;
-      if (tid == 0) {
-        sh.take = 0;
-        sh.n1 = 0;
-      }
+      if (tid == 0) sh.n1 = 0;
       __syncthreads();
       PbAppend app{FB, &sh.n1};
       if (l > 0) {  // level 0: frontier edges lie in no triangle
-        for (;;) {
-          const i32 i = wave_take(&sh.take);
-          if (i >= nf) break;
-          const i32 e1 = FA[i];
-          wave_edge(c, rows32(O, EL[e1]), e1, l, r, SW, (i32*)nullptr, p.owner_higher, app);
+        for (i32 c0 = 0; c0 < nf; c0 += PB_CH) {
+          const i32 cnt = min(PB_CH, nf - c0);
+          const i32 items = pb_chunk(O, EL, FA + c0, 0, cnt, false, sh);
+          for (i32 base = 0; base < items; base += PB_THREADS) {
+            const i32 gi = base + tid;
+            i32 x0 = -1, x1 = -1;
+            if (gi < items) {
+              i32 k, js, jl;
+              pb_item(A, sh, cnt, gi, k, js, jl);
+              if (jl >= 0) wave_triangle(EID[js], EID[jl], sh.e1[k], l, r, SW, nullptr, p.owner_higher, x0, x1);
+            }
+            app.add(x0, x1);
+          }
+          __syncthreads();  // the chunk's LDS is rewritten by the next one
         }
       }
       __syncthreads();
@@ -350,7 +403,7 @@ __device__ void pb_graph(const PbArgs& p, i32 g, PbShared& sh, i32* lsw) {
   __syncthreads();  // SW (LDS) is reused by the next graph
 }
 
-__global__ __launch_bounds__(PB_THREADS) void k_batch_persist(PbArgs p) {
+__global__ __launch_bounds__(PB_THREADS, PB_MIN_WAVES) void k_batch_persist(PbArgs p) {
   extern __shared__ i32 lsw[];  // PB_LDS_EDGES support words
   __shared__ PbShared sh;
   for (;;) {

@@ -43,6 +43,12 @@ struct Ctl {
   i32 chosen[TRUSS_NUM_CHOICES];  // rounds launched with each truss_choice
   i32 round_done;     // a round kernel ran; k_decide ends the round
   struct LoopSnap* snap;  // host-mapped loop-state slots (pipelined host loop) or null
+  // multi-round launch (k_psl_multi): next-frontier counters of rounds r % 3 (zeroed by
+  // the decision before the launch), grid-barrier arrivals and generation, and a flag
+  // set when a barrier's bounded wait ran out
+  i32 mcnt[3];
+  u32 bar_count, bar_gen;
+  i32 bar_timeout;
 };
 
 // Adjacency with edge ids: rows off[u]..off[u+1] of adj (sorted) and eid.

@@ -109,7 +109,8 @@ def test_training_fits_a_known_function(gpu_lib):
     rng = np.random.default_rng(4)
     X = rng.uniform(0, 10, (2000, 6)).astype(np.float32)
     T = np.stack([X[:, 0] * 0.5 + np.sin(X[:, 1]), X[:, 2] - X[:, 3], np.abs(X[:, 4] - 5), X[:, 5] ** 0.5,
-                  X[:, 0] * 0.1], axis=1).astype(np.float32)
+                  X[:, 0] * 0.1, np.maximum(X[:, 1], X[:, 2]) * 0.3], axis=1).astype(np.float32)
+    assert T.shape[1] == K
     M = (rng.random(T.shape) < 0.8).astype(np.float32)
     W, hist = tuner.train(X, T, M, steps=1500, lr=3e-3)
     assert hist[-1] < 0.05 * hist[0]
@@ -140,14 +141,19 @@ def test_trained_model_gain_on_held_out_traces(gpu_lib):
     if not os.path.exists(tuner.DEFAULT_WEIGHTS):
         pytest.skip("no trained cost model shipped")
     W = tuner.load_weights()
-    g = gg.rmat(19, 16, seed=2)  # not a training workload
-    rounds = tuner.collect_rounds(g.offsets, g.adj)
+    # workloads the model was not trained on: R-MAT scale 21 (another seed) and the
+    # 64-graph batch recipe as one union graph
+    rounds = []
+    for g in (gg.rmat(21, 16, seed=2), gg.workload("batch64", seed=3).union()):
+        rounds += tuner.collect_rounds(g.offsets, g.adj, repeats=2)
     choice = tuner.learned_choices(W, rounds)  # the model above the size the loop consults it at
     learned = tuner.evaluate(rounds, lambda r, it=iter(choice): int(next(it)))
     heur = tuner.evaluate(rounds, lambda r: tuner.heuristic_choice(r["frontier"]))
-    say("held-out rmat19: learned", learned, "heuristic", heur)
-    # the model must not lose to the heuristic by more than noise, and beats picking at random
-    assert learned["total_us"] <= 1.05 * heur["total_us"]
+    departs = sum(int(c) != tuner.heuristic_choice(r["frontier"]) for c, r in zip(choice, rounds))
+    say("held-out: learned", learned, "heuristic", heur, "rounds", len(rounds), "departures", departs)
+    # the model's choices cost less than the heuristic's, and than picking at random
+    assert departs > 0
+    assert learned["total_us"] < heur["total_us"]
     rng = np.random.default_rng(0)
     rand = tuner.evaluate(rounds, lambda r: int(rng.choice(tuner.valid_choices(r["frontier"]))))
     assert learned["total_us"] < rand["total_us"]

@@ -114,6 +114,9 @@ def test_support_and_edge_list(gpu_lib, make):
     dict(device_loop="graph", force_choice="wave"),
     dict(device_loop="device", force_choice="wave", steps_per_sync=2),
     dict(device_loop="pipelined", force_choice="wave", compact=False),
+    dict(multi_round=True),
+    dict(device_loop="host", multi_round=True),
+    dict(multi_round=True, variant="merge"),
 ])
 def test_medium_graphs(gpu_lib, make, opts):
     g = make()
@@ -271,6 +274,7 @@ def test_full_size_against_stored_oracle(gpu_lib, name):
     dict(compact=False),
     dict(owner_rule=1),
     dict(force_choice="wave"),
+    dict(multi_round=True),
 ])
 def test_full_size_variants_rmat20(gpu_lib, opts):
     """Launch variants and loop drivers at the full R-MAT scale-20 size: every one gives
