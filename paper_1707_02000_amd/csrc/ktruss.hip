@@ -82,10 +82,13 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_kt_compress(i32 n, i32* par) {
 // in any order.  In the canonical row-major order the lanes of a wave mostly share
 // one root (consecutive edges of one row, or one large k-truss), so the lanes
 // that share the first active lane's root take their minimum first and one atomic
-// reaches memory for them; every other lane takes its own atomic.
+// reaches memory for them; every other lane takes its own atomic.  A set's value
+// only decreases, so an offer no smaller than a plain read of it (possibly older,
+// hence no smaller than the current value) is dropped without an atomic: with
+// one giant k-truss the low ids arrive first and most waves end there.
 __global__ __launch_bounds__(PKT_BLOCK) void k_kt_first(i64 m, const i32* __restrict__ eu,
                                                        const i32* __restrict__ tau, i32 k,
-                                                       const i32* __restrict__ par, i32* __restrict__ first,
+                                                       const i32* __restrict__ par, i32* first,
                                                        const u32* __restrict__ err) {
   if (*err) return;
   const i64 stride = (i64)gridDim.x * PKT_BLOCK;
@@ -98,8 +101,8 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_kt_first(i64 m, const i32* __rest
     const int lead = __ffsll((unsigned long long)act) - 1;
     const i32 rl = __shfl(r, lead);
     const i32 mn = wave_min_i32(r == rl ? (i32)e : INT_MAX);
-    if (lane_id() == lead) atomicMin(&first[rl], mn);
-    if (r >= 0 && r != rl) atomicMin(&first[r], (i32)e);
+    if (lane_id() == lead && mn < first[rl]) atomicMin(&first[rl], mn);
+    if (r >= 0 && r != rl && (i32)e < first[r]) atomicMin(&first[r], (i32)e);
   }
 }
 
