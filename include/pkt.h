@@ -72,8 +72,16 @@ typedef enum {
   TRUSS_CHOICE_WAVE = 5,         /* one wave per frontier edge, no work scan: the two rows merged
                                     in 64-entry chunks (binary search in the longer row when it is
                                     over 8 times the shorter), then finalize */
-  TRUSS_NUM_CHOICES = 6
+  TRUSS_CHOICE_HASH = 6,         /* one wave per frontier edge, no work scan: the longer row (up to
+                                    256 entries) hashed into LDS and probed by the shorter row's
+                                    entries (longer rows as TRUSS_CHOICE_WAVE), then finalize */
+  TRUSS_NUM_CHOICES = 7
 } truss_choice;
+
+/* Launch choices the cost model scores (TRUSS_VARIANT_LEARNED): the first six.  The LDS-hash
+ * round stays outside its choice space: it is slower than the merge round on every traced
+ * workload, and scoring it made the model's held-out choices worse. */
+#define TRUSS_MODEL_CHOICES 6
 
 /* Policy that picks the launch of every round. */
 typedef enum {
@@ -98,7 +106,7 @@ typedef enum {
 typedef struct {
   int32_t level;             /* support level at the start */
   int32_t kind;              /* 0 level scan, 1 fused launch, 2 wide launch sequence, 3 one wave
-                                per edge */
+                                per edge (merge), 4 one wave per edge (LDS hash) */
   int32_t choice;            /* truss_choice launched (kinds 1 and 2) */
   int32_t rounds;            /* frontier rounds completed by the sequence */
   int64_t frontier;          /* frontier size at the start */
@@ -403,7 +411,7 @@ truss_status truss_decompose_batched(int32_t num_graphs, const int64_t* graph_vt
 /*
  * The launch cost model of TRUSS_VARIANT_LEARNED: an fp32 MLP from the
  * TRUSS_NUM_FEATURES frontier features to one predicted log2(device microseconds)
- * per truss_choice (3 hidden layers of 64, ReLU).  Weights are
+ * per scored launch choice (TRUSS_MODEL_CHOICES, 3 hidden layers of 64, ReLU).  Weights are
  * truss_mlp_num_params() floats in device memory: feature mean and standard
  * deviation (for normalisation), then each layer's weights and biases.  Rows of X
  * are feature vectors, rows of T the measured log2 times, rows of M 1 where a

@@ -23,7 +23,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpkt.so")
 
 VARIANTS = {"auto": 0, "bsearch": 1, "merge": 2, "fixed": 3, "learned": 4}
-CHOICES = ["fused", "fused_narrow", "wide", "wide_narrow", "wide_gallop", "wave"]
+CHOICES = ["fused", "fused_narrow", "wide", "wide_narrow", "wide_gallop", "wave", "hash"]
+MODEL_CHOICES = 6  # the first six: the ones the cost model scores (TRUSS_MODEL_CHOICES)
 LOOP_MODES = {"host": 0, "device": 1, "graph": 2, "pipelined": 3}  # truss_options.device_loop
 
 

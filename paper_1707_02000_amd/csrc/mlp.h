@@ -18,7 +18,7 @@
 
 #define MLP_IN 6
 #define MLP_H 64
-#define MLP_OUT TRUSS_NUM_CHOICES
+#define MLP_OUT TRUSS_MODEL_CHOICES
 
 #define MLP_OFF_MU 0
 #define MLP_OFF_SIG (MLP_OFF_MU + MLP_IN)

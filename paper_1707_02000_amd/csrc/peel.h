@@ -109,7 +109,7 @@ __device__ __forceinline__ int mlp_decide(const float* y, i32 ncurr) {
   const int h = ncurr <= FUSED_THRESHOLD ? TRUSS_CHOICE_FUSED : TRUSS_CHOICE_WIDE;
   int best = -1;
   float bv = INFINITY;
-  for (int k = 0; k < TRUSS_NUM_CHOICES; ++k) {
+  for (int k = 0; k < MLP_OUT; ++k) {
     if ((k == TRUSS_CHOICE_FUSED || k == TRUSS_CHOICE_FUSED_NARROW) && ncurr > SMALL_FRONTIER) continue;
     if (!isfinite(y[k])) return h;
     if (y[k] < bv) {

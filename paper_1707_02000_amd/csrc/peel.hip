@@ -86,6 +86,7 @@ __device__ __forceinline__ bool is_wide(int c) {
   return c == TRUSS_CHOICE_WIDE || c == TRUSS_CHOICE_WIDE_NARROW || c == TRUSS_CHOICE_WIDE_GALLOP;
 }
 __device__ __forceinline__ bool is_wave(int c) { return c == TRUSS_CHOICE_WAVE; }
+__device__ __forceinline__ bool is_hash(int c) { return c == TRUSS_CHOICE_HASH; }
 
 // The built-in heuristic: fused launch up to FUSED_THRESHOLD frontier edges (the
 // threshold the tuner's trace search picked), else the wide sequence.
@@ -1110,6 +1111,36 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_psl_wave(PeelArgs a) {
   ba.flush(next, &ctl->nnext);
 }
 
+// Round of one wave per frontier edge with the longer row hashed into LDS
+// (TRUSS_CHOICE_HASH): workgroups of one wave, HASH_BLOCKS of them; workgroup g
+// takes frontier edges g, g + HASH_BLOCKS, ...  No work prefix, no scan launches.
+#define HASH_BLOCKS 8192
+__global__ __launch_bounds__(PKT_WAVE) void k_psl_hash(PeelArgs a) {
+  Ctl* ctl = a.ctl;
+  __shared__ CtlView v;
+  __shared__ BlockAppend ba;
+  __shared__ i32 keys[WAVE_HASH_SLOTS];
+  __shared__ unsigned short pos[WAVE_HASH_SLOTS];
+  load_view(ctl, &v);
+  if (v.done || v.ncurr == 0 || !is_hash(v.choice)) return;
+  const i32 nc = v.ncurr, l = v.level, sel = v.sel, r = v.r;
+  const i32* curr = cur_of(a, sel);
+  i32* next = next_of(a, sel);
+  const Csr c = a.csr.pick(v.csel);
+  mark_prev(a, sel, r, v.nprev, (i64)blockIdx.x * PKT_WAVE + threadIdx.x, (i64)gridDim.x * PKT_WAVE);
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->round_done = 1;
+  if (threadIdx.x == 0) ba.n = 0;
+  __syncthreads();
+  WaveAppend app{&ba, next, &ctl->nnext};
+  if (l > 0) {  // level 0: frontier edges lie in no triangle
+    for (i64 i = blockIdx.x; i < nc; i += gridDim.x) {
+      const i32 e1 = curr[i];
+      wave_edge_hash(c, rows_of(c, a.el[e1]), e1, l, r, a.sw, a.order, a.owner_higher, app, keys, pos);
+    }
+  }
+  ba.flush(next, &ctl->nnext);
+}
+
 // One block after a level scan or a round: ends the round the previous launch
 // ran (Ctl::round_done), goes on alone while the work stays small, then picks
 // the launch of the frontier left, if any (only when none is picked yet).
@@ -1317,6 +1348,10 @@ static truss_status launch_round(const Work& w, const PeelArgs& a, const Ctl& hc
     *kind = 3;
     hipLaunchKernelGGL(k_psl_wave, dim3(WIDE_BLOCKS), dim3(WIDE_THREADS), 0, s, a);
     hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a, (i64)0, 0);
+  } else if (hc.choice == TRUSS_CHOICE_HASH) {
+    *kind = 4;
+    hipLaunchKernelGGL(k_psl_hash, dim3(HASH_BLOCKS), dim3(PKT_WAVE), 0, s, a);
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a, (i64)0, 0);
   } else {
     *kind = 2;
     // level 0: frontier edges lie in no triangle, nothing to intersect or scan
@@ -1350,6 +1385,7 @@ static truss_status enqueue_step(const Work& w, const PeelArgs& a, int G, hipStr
   hipLaunchKernelGGL(k_psl_bsearch, dim3(WIDE_BLOCKS), dim3(WIDE_THREADS), 0, s, a, (const i64*)w.X);
   if (prof) PKT_HIP(prof->mark(s));
   hipLaunchKernelGGL(k_psl_wave, dim3(WIDE_BLOCKS), dim3(WIDE_THREADS), 0, s, a);
+  hipLaunchKernelGGL(k_psl_hash, dim3(HASH_BLOCKS), dim3(PKT_WAVE), 0, s, a);
   PKT_LAUNCH_CHECK();
   return TRUSS_OK;
 }
@@ -1363,7 +1399,7 @@ static truss_status enqueue_step(const Work& w, const PeelArgs& a, int G, hipStr
 // work prefix of a wide round, the chunk offsets of a level scan) comes from the
 // launch just before it in the same sequence, under the same loop state.
 
-enum SeqKind { SEQ_SCAN = 0, SEQ_DECIDE = 1, SEQ_FUSED = 2, SEQ_WIDE = 3, SEQ_WAVE = 4 };
+enum SeqKind { SEQ_SCAN = 0, SEQ_DECIDE = 1, SEQ_FUSED = 2, SEQ_WIDE = 3, SEQ_WAVE = 4, SEQ_HASH = 5 };
 
 #define PIPE_DEPTH 2  // sequences in flight beyond the last state seen (default; measured best)
 #define PIPE_MAX 6
@@ -1374,6 +1410,7 @@ inline int seq_kind(i32 ncurr, i32 choice) {
   if (choice == CHOICE_NONE) return SEQ_DECIDE;
   if (choice == TRUSS_CHOICE_FUSED || choice == TRUSS_CHOICE_FUSED_NARROW) return SEQ_FUSED;
   if (choice == TRUSS_CHOICE_WAVE) return SEQ_WAVE;
+  if (choice == TRUSS_CHOICE_HASH) return SEQ_HASH;
   return SEQ_WIDE;
 }
 
@@ -1398,6 +1435,8 @@ static truss_status enqueue_seq(const Work& w, const PeelArgs& a, int kind, int 
     }
   } else if (kind == SEQ_WAVE) {
     hipLaunchKernelGGL(k_psl_wave, dim3(WIDE_BLOCKS), dim3(WIDE_THREADS), 0, s, a);
+  } else if (kind == SEQ_HASH) {
+    hipLaunchKernelGGL(k_psl_hash, dim3(HASH_BLOCKS), dim3(PKT_WAVE), 0, s, a);
   } else if (kind == SEQ_WIDE) {
     PKT_HIP((scan_launch<WideLen, true>(WideLen{a}, w.partial, w.X, &w.ctl->scan_arrive, s)));
     const int blocks = choice == TRUSS_CHOICE_WIDE_NARROW ? WIDE_NARROW_BLOCKS : WIDE_BLOCKS;
@@ -1606,8 +1645,10 @@ truss_status run_single(const Work& w, const truss_options& opt, truss_stats* st
       while (nfl < depth) {
         const i64 q = ++snap_seq;
         const int choice = known ? cur.choice
-                                 : (ks == SEQ_FUSED ? TRUSS_CHOICE_FUSED
-                                                    : (ks == SEQ_WAVE ? TRUSS_CHOICE_WAVE : TRUSS_CHOICE_WIDE));
+                                 : (ks == SEQ_FUSED  ? TRUSS_CHOICE_FUSED
+                                    : ks == SEQ_WAVE ? TRUSS_CHOICE_WAVE
+                                    : ks == SEQ_HASH ? TRUSS_CHOICE_HASH
+                                                     : TRUSS_CHOICE_WIDE);
         truss_status r = enqueue_seq(w, a, ks, choice, cur.nalive, s, prof, q);
         if (r) return r;
         fl[nfl++] = Flight{q, ks};
@@ -1632,7 +1673,7 @@ truss_status run_single(const Work& w, const truss_options& opt, truss_stats* st
       }
       if (f.kind == SEQ_SCAN && seq_kind(prev.ncurr, prev.choice) == SEQ_SCAN) {
         const int k = seq_kind(cur.ncurr, cur.choice);
-        if (k == SEQ_FUSED || k == SEQ_WIDE || k == SEQ_WAVE) after_scan = k;
+        if (k == SEQ_FUSED || k == SEQ_WIDE || k == SEQ_WAVE || k == SEQ_HASH) after_scan = k;
       }
       if (opt.compact && cur.compact) {
         PKT_HIP(hipStreamSynchronize(s));  // lets the sequences in flight finish

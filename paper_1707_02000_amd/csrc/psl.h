@@ -181,6 +181,70 @@ __device__ void wave_edge(const Csr& c, const Rows& r, i32 e1, i32 l, i32 rd, i3
   wave_intersect(c.adj, r, h);
 }
 
+// LDS hash variant: the longer row (at most WAVE_HASH_CAP entries) goes into an
+// open-addressing table in LDS (key = vertex, value = its position in the row;
+// WAVE_HASH_SLOTS slots, linear probing, multiplicative hash), then every lane
+// probes its shorter-row entries.  Longer rows take wave_intersect.  Called by a
+// workgroup of exactly one wave (its barriers are the wave's own), every argument
+// uniform; keys / pos are that workgroup's LDS.
+#define WAVE_HASH_CAP 256
+#define WAVE_HASH_SLOTS (2 * WAVE_HASH_CAP)
+__device__ __forceinline__ u32 wave_hash_slot(i32 w) { return ((u32)w * 0x9E3779B1u) >> (32 - 9); }
+static_assert(WAVE_HASH_SLOTS == 512, "wave_hash_slot takes the top 9 bits");
+
+template <class Hit>
+__device__ void wave_intersect_hash(const i32* __restrict__ adj, const Rows& r, Hit& hit, i32* keys,
+                                    unsigned short* pos) {
+  const int lane = lane_id();
+  const i64 a = r.slen, b = r.le - r.lb;
+  if (a == 0 || b == 0) return;
+  if (b > WAVE_HASH_CAP) {
+    wave_intersect(adj, r, hit);
+    return;
+  }
+  for (int k = lane; k < WAVE_HASH_SLOTS; k += PKT_WAVE) keys[k] = -1;
+  __syncthreads();
+  for (i32 j = lane; j < (i32)b; j += PKT_WAVE) {
+    const i32 w = adj[r.lb + j];
+    u32 h = wave_hash_slot(w);
+    for (;;) {  // b <= half the slots: a free slot is always found
+      const i32 old = atomicCAS(&keys[h], -1, w);
+      if (old == -1) {
+        pos[h] = (unsigned short)j;
+        break;
+      }
+      h = (h + 1) & (WAVE_HASH_SLOTS - 1);
+    }
+  }
+  __syncthreads();
+  for (i64 i = 0; i < a; i += PKT_WAVE) {
+    const bool sv = i + lane < a;
+    i64 jl = -1;
+    if (sv) {
+      const i32 s = adj[r.sb + i + lane];
+      u32 h = wave_hash_slot(s);
+      for (;;) {
+        const i32 k = keys[h];
+        if (k == s) {
+          jl = r.lb + pos[h];
+          break;
+        }
+        if (k == -1) break;
+        h = (h + 1) & (WAVE_HASH_SLOTS - 1);
+      }
+    }
+    hit(jl >= 0, r.sb + i + lane, jl);
+  }
+  __syncthreads();  // the table is the next edge's
+}
+
+template <class Append>
+__device__ void wave_edge_hash(const Csr& c, const Rows& r, i32 e1, i32 l, i32 rd, i32* sw, i32* order,
+                               int owner_higher, Append& app, i32* keys, unsigned short* pos) {
+  PeelHit<Append> h{c.eid, e1, l, rd, sw, order, owner_higher, &app};
+  wave_intersect_hash(c.adj, r, h, keys, pos);
+}
+
 // |N(u) ∩ N(v)| of the rows r, by the calling wave (every lane gets the count).
 struct CountHit {
   i32 n = 0;

@@ -22,7 +22,7 @@ import os
 
 import numpy as np
 
-from . import CHOICES, NUM_FEATURES, _check, _stream, _torch, alloc_workspace, load, truss_decompose
+from . import CHOICES, MODEL_CHOICES, NUM_FEATURES, _check, _stream, _torch, alloc_workspace, load, truss_decompose
 
 FUSED_LIMIT = 2048  # frontier edges the fused launch accepts
 DATA_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data")
@@ -30,7 +30,7 @@ DEFAULT_WEIGHTS = os.path.join(DATA_DIR, "cost_model.json")
 
 
 def valid_choices(frontier: int):
-    return [c for c in range(len(CHOICES)) if c >= 2 or frontier <= FUSED_LIMIT]
+    return [c for c in range(MODEL_CHOICES) if c >= 2 or frontier <= FUSED_LIMIT]
 
 
 def collect_rounds(offsets, adj, *, repeats: int = 1, capacity: int = 1 << 20):
@@ -42,7 +42,7 @@ def collect_rounds(offsets, adj, *, repeats: int = 1, capacity: int = 1 << 20):
     off = offsets if hasattr(offsets, "is_cuda") else torch.from_numpy(np.asarray(offsets)).cuda()
     adj_t = adj if hasattr(adj, "is_cuda") else torch.from_numpy(np.asarray(adj)).cuda()
     per_choice = {}
-    for c in range(len(CHOICES)):
+    for c in range(MODEL_CHOICES):
         best = None
         for _ in range(max(1, repeats)):
             _, st = truss_decompose(off, adj_t, validate=False, force_choice=c, single_round=True,
@@ -60,7 +60,7 @@ def collect_rounds(offsets, adj, *, repeats: int = 1, capacity: int = 1 << 20):
     for k in sorted(ref):
         r0 = ref[k]
         us = {}
-        for c in range(len(CHOICES)):
+        for c in range(MODEL_CHOICES):
             r = per_choice[c].get(k)
             if r is not None and r["choice"] == c:  # a forced choice that was invalid fell back
                 us[c] = r["ms"] * 1e3
@@ -71,7 +71,7 @@ def collect_rounds(offsets, adj, *, repeats: int = 1, capacity: int = 1 << 20):
 
 def dataset(rounds):
     """X (n, 6) features, T (n, K) log2 microseconds, M (n, K) measured mask, ncurr (n,)."""
-    n, k = len(rounds), len(CHOICES)
+    n, k = len(rounds), MODEL_CHOICES
     X = np.zeros((n, NUM_FEATURES), np.float32)
     T = np.zeros((n, k), np.float32)
     M = np.zeros((n, k), np.float32)
@@ -141,7 +141,7 @@ def predict(W, X):
     lib = load()
     n = int(X.shape[0])
     Xd = _dev(np.asarray(X, np.float32), torch)
-    Y = torch.empty((n, len(CHOICES)), dtype=torch.float32, device="cuda")
+    Y = torch.empty((n, MODEL_CHOICES), dtype=torch.float32, device="cuda")
     nb = lib.truss_mlp_workspace_bytes(n)
     _buf, wptr = alloc_workspace(nb)
     _check(lib.truss_mlp_forward(ctypes.c_void_p(Xd.data_ptr()), n, ctypes.c_void_p(W.data_ptr()),
@@ -157,7 +157,7 @@ def choose_batch(W, X, ncurr):
     Xd = _dev(np.asarray(X, np.float32), torch)
     Nd = _dev(np.asarray(ncurr, np.int32), torch)
     C = torch.empty(n, dtype=torch.int32, device="cuda")
-    Y = torch.empty((n, len(CHOICES)), dtype=torch.float32, device="cuda")
+    Y = torch.empty((n, MODEL_CHOICES), dtype=torch.float32, device="cuda")
     _check(lib.truss_mlp_choose(ctypes.c_void_p(Xd.data_ptr()), ctypes.c_void_p(Nd.data_ptr()), n,
                                 ctypes.c_void_p(W.data_ptr()), ctypes.c_void_p(C.data_ptr()),
                                 ctypes.c_void_p(Y.data_ptr()), _stream(torch, None)))

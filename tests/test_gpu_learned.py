@@ -13,7 +13,7 @@ import oracle
 from oracle import mlp as ref
 
 pytestmark = pytest.mark.gpu
-K = 6  # truss_choice values (TRUSS_NUM_CHOICES)
+K = 6  # launch choices the model scores (TRUSS_MODEL_CHOICES)
 
 
 def say(*a):

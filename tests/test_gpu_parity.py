@@ -61,6 +61,7 @@ def test_small_graphs(gpu_lib, name, g):
     want = oracle.truss(g)
     assert np.array_equal(gpu_tau(gpu_lib, g), want)
     assert np.array_equal(gpu_tau(gpu_lib, g, force_choice="wave"), want)
+    assert np.array_equal(gpu_tau(gpu_lib, g, force_choice="hash"), want)
 
 
 @pytest.mark.parametrize("make", [
@@ -116,6 +117,10 @@ def test_support_and_edge_list(gpu_lib, make):
     dict(device_loop="pipelined", force_choice="wave", compact=False),
     dict(multi_round=True),
     dict(device_loop="host", multi_round=True),
+    dict(force_choice="hash"),
+    dict(force_choice="hash", owner_rule=1, compact=False),
+    dict(device_loop="host", force_choice="hash"),
+    dict(device_loop="graph", force_choice="hash"),
     dict(multi_round=True, variant="merge"),
 ])
 def test_medium_graphs(gpu_lib, make, opts):
@@ -274,6 +279,7 @@ def test_full_size_against_stored_oracle(gpu_lib, name):
     dict(compact=False),
     dict(owner_rule=1),
     dict(force_choice="wave"),
+    dict(force_choice="hash"),
     dict(multi_round=True),
 ])
 def test_full_size_variants_rmat20(gpu_lib, opts):

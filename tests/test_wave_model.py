@@ -96,3 +96,48 @@ def test_interleaved_and_disjoint_ranges():
     assert got == [] and steps <= 10
     got, _ = merge_model(L2, S2)
     assert got == []
+
+
+SLOTS, CAP = 512, 256
+
+
+def slot(w):
+    return ((int(w) * 0x9E3779B1) & 0xFFFFFFFF) >> (32 - 9)
+
+
+def hash_model(S, L):
+    """The LDS-hash variant (wave_intersect_hash) lane by lane: the longer row into an
+    open-addressing table of 512 slots (linear probing) with each key's position, then
+    every shorter-row entry probed."""
+    assert len(L) <= CAP
+    keys = [-1] * SLOTS
+    pos = [0] * SLOTS
+    for j, w in enumerate(L):
+        h = slot(w)
+        while keys[h] != -1:
+            h = (h + 1) & (SLOTS - 1)
+        keys[h], pos[h] = int(w), j
+    found = []
+    for i, s in enumerate(S):
+        h = slot(s)
+        while keys[h] != -1:
+            if keys[h] == s:
+                found.append((i, pos[h]))
+                break
+            h = (h + 1) & (SLOTS - 1)
+    return found
+
+
+@pytest.mark.parametrize("a,b", [(1, 1), (5, 256), (256, 256), (40, 100), (300, 256), (3, 17)])
+@pytest.mark.parametrize("overlap", [0.0, 0.5, 1.0])
+def test_hash_finds_every_common_entry_once(a, b, overlap):
+    rng = np.random.default_rng(7 * a + b)
+    S, L = rows(rng, a, b, max(4 * (a + b), 64), overlap)
+    assert sorted(hash_model(S, L)) == truth(S, L)
+
+
+def test_hash_clusters_and_large_ids():
+    # ids that share the hash's top bits cluster into long probe runs; ids near 2^31
+    L = np.array(sorted({(k << 23) for k in range(200)} | {2**31 - 2 - k for k in range(56)}), np.int64)
+    S = L[::3].copy()
+    assert sorted(hash_model(S, L)) == truth(S, L)
