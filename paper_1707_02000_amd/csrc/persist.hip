@@ -113,16 +113,47 @@ __device__ i32 pb_chunk(const i32* __restrict__ O, const int2* __restrict__ EL, 
   return (i32)tot;
 }
 
-// Item g of the chunk (g < items): its edge k, and the slots of its shorter-row
-// entry and of the same vertex in the longer row (jl = -1 if absent).
-__device__ __forceinline__ void pb_item(const i32* __restrict__ A, const PbShared& sh, i32 cnt, i32 g, i32& k,
-                                        i32& js, i32& jl) {
-  k = (i32)upper_bound_dev(sh.P, (i32)0, cnt + 1, g) - 1;
-  js = sh.sb[k] + (g - sh.P[k]);
-  const i32 w = A[js];
-  const i32 lo = sh.lb[k], hi = lo + sh.ll[k];
-  const i32 q = lower_bound_dev(A, lo, hi, w);
-  jl = (q < hi && A[q] == w) ? q : -1;
+// Items g0 and g1 of the chunk, side by side so that their dependent loads overlap
+// (a lane has two chains in flight): for each, its edge k (-1 when g >= items), the
+// slot js of its shorter-row entry and the slot jl of the same vertex in the longer
+// row (-1 if absent).  Both binary searches run in lockstep, one probe of each per
+// step; a finished search keeps probing its row's first slot (always inside the
+// row: b may have reached the row's end, which can be one past the graph).
+__device__ __forceinline__ void pb_item2(const i32* __restrict__ A, const PbShared& sh, i32 cnt, i32 items, i32 g0,
+                                         i32 g1, i32& k0, i32& js0, i32& jl0, i32& k1, i32& js1, i32& jl1) {
+  const bool v0 = g0 < items, v1 = g1 < items;
+  k0 = v0 ? (i32)upper_bound_dev(sh.P, (i32)0, cnt + 1, g0) - 1 : -1;
+  k1 = v1 ? (i32)upper_bound_dev(sh.P, (i32)0, cnt + 1, g1) - 1 : -1;
+  const i32 q0 = v0 ? k0 : 0, q1 = v1 ? k1 : 0;
+  js0 = sh.sb[q0] + (v0 ? g0 - sh.P[q0] : 0);
+  js1 = sh.sb[q1] + (v1 ? g1 - sh.P[q1] : 0);
+  const i32 w0 = A[js0], w1 = A[js1];
+  const i32 r0 = sh.lb[q0], r1 = sh.lb[q1];  // row starts: rows of edges hold >= 1 entry
+  i32 b0 = r0, n0 = v0 ? sh.ll[q0] : 0;
+  i32 b1 = r1, n1 = v1 ? sh.ll[q1] : 0;
+  const i32 e0 = b0 + n0, e1 = b1 + n1;
+  while (n0 > 0 || n1 > 0) {  // lower bound: b + n stays the end of the candidates
+    const i32 h0 = n0 >> 1, h1 = n1 >> 1;
+    const i32 x0 = A[n0 > 0 ? b0 + h0 : r0], x1 = A[n1 > 0 ? b1 + h1 : r1];
+    if (n0 > 0) {
+      if (x0 < w0) {
+        b0 += h0 + 1;
+        n0 -= h0 + 1;
+      } else {
+        n0 = h0;
+      }
+    }
+    if (n1 > 0) {
+      if (x1 < w1) {
+        b1 += h1 + 1;
+        n1 -= h1 + 1;
+      } else {
+        n1 = h1;
+      }
+    }
+  }
+  jl0 = (v0 && b0 < e0 && A[b0] == w0) ? b0 : -1;
+  jl1 = (v1 && b1 < e1 && A[b1] == w1) ? b1 : -1;
 }
 
 // Appends of one round to the next frontier: per wave, one LDS reservation.
@@ -250,22 +281,24 @@ __device__ void pb_graph(const PbArgs& p, i32 g, PbShared& sh, i32* lsw) {
   for (i32 c0 = 0; c0 < m; c0 += PB_CH) {
     const i32 cnt = min(PB_CH, m - c0);
     const i32 items = pb_chunk(O, EL, nullptr, c0, cnt, false, sh);
-    for (i32 base = 0; base < items; base += PB_THREADS) {
-      const i32 gi = base + tid;
-      i32 k = -1, js, jl = -1;
-      if (gi < items) pb_item(A, sh, cnt, gi, k, js, jl);
-      u64 todo = __ballot(k >= 0);
-      const u64 hits = __ballot(jl >= 0);
-      while (todo) {  // lanes' edges are non-decreasing: a few segments per wave
-        const int lead = __ffsll((unsigned long long)todo) - 1;
-        const i32 kl = __shfl(k, lead);
-        const u64 same = __ballot(k == kl);
-        const i32 c = (i32)__popcll(hits & same);
-        if (lane == lead && c) {
-          atomicAdd(&SW[c0 + kl], c << SW_SHIFT);  // state bits stay ST_ALIVE
-          tri3 += c;
+    for (i32 base = 0; base < items; base += 2 * PB_THREADS) {
+      i32 k[2], js[2], jl[2];
+      pb_item2(A, sh, cnt, items, base + tid, base + PB_THREADS + tid, k[0], js[0], jl[0], k[1], js[1], jl[1]);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        u64 todo = __ballot(k[h] >= 0);
+        const u64 hits = __ballot(jl[h] >= 0);
+        while (todo) {  // lanes' edges are non-decreasing: a few segments per wave
+          const int lead = __ffsll((unsigned long long)todo) - 1;
+          const i32 kl = __shfl(k[h], lead);
+          const u64 same = __ballot(k[h] == kl);
+          const i32 c = (i32)__popcll(hits & same);
+          if (lane == lead && c) {
+            atomicAdd(&SW[c0 + kl], c << SW_SHIFT);  // state bits stay ST_ALIVE
+            tri3 += c;
+          }
+          todo &= ~same;
         }
-        todo &= ~same;
       }
     }
     __syncthreads();  // the chunk's LDS is rewritten by the next one
@@ -354,15 +387,17 @@ __device__ void pb_graph(const PbArgs& p, i32 g, PbShared& sh, i32* lsw) {
         for (i32 c0 = 0; c0 < nf; c0 += PB_CH) {
           const i32 cnt = min(PB_CH, nf - c0);
           const i32 items = pb_chunk(O, EL, FA + c0, 0, cnt, false, sh);
-          for (i32 base = 0; base < items; base += PB_THREADS) {
-            const i32 gi = base + tid;
-            i32 x0 = -1, x1 = -1;
-            if (gi < items) {
-              i32 k, js, jl;
-              pb_item(A, sh, cnt, gi, k, js, jl);
-              if (jl >= 0) wave_triangle(EID[js], EID[jl], sh.e1[k], l, r, SW, nullptr, p.owner_higher, x0, x1);
+          for (i32 base = 0; base < items; base += 2 * PB_THREADS) {
+            i32 k[2], js[2], jl[2];
+            pb_item2(A, sh, cnt, items, base + tid, base + PB_THREADS + tid, k[0], js[0], jl[0], k[1], js[1],
+                     jl[1]);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              i32 x0 = -1, x1 = -1;
+              if (jl[h] >= 0)
+                wave_triangle(EID[js[h]], EID[jl[h]], sh.e1[k[h]], l, r, SW, nullptr, p.owner_higher, x0, x1);
+              app.add(x0, x1);
             }
-            app.add(x0, x1);
           }
           __syncthreads();  // the chunk's LDS is rewritten by the next one
         }
