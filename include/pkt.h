@@ -162,7 +162,16 @@ typedef struct {
                                 cooperative launch of 64 workgroups that meet at a grid barrier
                                 between rounds (measured slower than one launch per round on
                                 this GPU; default 0) */
-  int32_t reserved[7];       /* zero (room for later options without a layout change) */
+  int32_t relabel;           /* 1 = truss_decompose and truss_decompose32 relabel the vertices by
+                                increasing (degree, id) on the device, decompose the relabelled
+                                graph and map its trussness (and peel_round) back to the input's
+                                edge order (default 1): the output does not change, the level loop
+                                runs faster because the high-degree rows it searches most sit
+                                together.  Needs the larger workspace truss_workspace_bytes gives
+                                for it; its time is counted in ms_build.  Not used by
+                                truss_support, truss_decompose32_static or the batched entry
+                                point */
+  int32_t reserved[6];       /* zero (room for later options without a layout change) */
 } truss_options;
 
 typedef struct {
@@ -173,7 +182,7 @@ typedef struct {
   int32_t t_max;         /* maximum trussness (0 when m = 0) */
   int32_t compactions;   /* adjacency rebuilds */
   float ms_validate;     /* phase times (ms, device events) */
-  float ms_build;        /* edge ids, orientation */
+  float ms_build;        /* edge ids, orientation; with relabel = 1 also the relabelling */
   float ms_support;
   float ms_peel;         /* level loop: scans, sub-levels, compactions */
   float ms_total;
@@ -192,8 +201,11 @@ typedef struct {
 /* Fills *opt with the defaults listed above. */
 void truss_default_options(truss_options* opt);
 
-/* Workspace bytes needed by truss_decompose for a graph with n vertices and
- * two_m adjacency slots (= offsets[n]).  opt may be NULL (defaults). */
+/* Workspace bytes needed by truss_decompose and truss_decompose32 for a graph with
+ * n vertices and two_m adjacency slots (= offsets[n]) under the options *opt (NULL =
+ * defaults).  With relabel = 1 (the default) this adds, beyond the decomposition's
+ * own arrays, the relabelled CSR and the permutation: about 16 bytes per edge and
+ * 40 per vertex more. */
 truss_status truss_workspace_bytes(int32_t n, int64_t two_m, const truss_options* opt, size_t* bytes);
 
 /*

@@ -66,7 +66,8 @@ class Options(ctypes.Structure):
         ("single_round", ctypes.c_int32),
         ("peel_round", ctypes.c_void_p),
         ("multi_round", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 7),
+        ("relabel", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 6),
     ]
 
 
@@ -205,7 +206,7 @@ def default_options() -> Options:
 
 def make_options(variant="auto", device_loop="pipelined", validate=True, owner_rule=0, compact=True,
                  steps_per_sync=0, mlp_weights=None, profile=False, force_choice=None,
-                 single_round=False, multi_round=False) -> Options:
+                 single_round=False, multi_round=False, relabel=True) -> Options:
     o = default_options()
     o.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
     o.device_loop = loop_mode(device_loop)
@@ -220,6 +221,7 @@ def make_options(variant="auto", device_loop="pipelined", validate=True, owner_r
         o.force_choice = CHOICES.index(force_choice) if isinstance(force_choice, str) else int(force_choice)
     o.single_round = int(bool(single_round))
     o.multi_round = int(bool(multi_round))
+    o.relabel = int(bool(relabel))
     return o
 
 
@@ -287,14 +289,15 @@ class Workspace:
 def truss_decompose(offsets, adj, *, variant="auto", device_loop="pipelined", validate=True, owner_rule=0,
                     compact=True, steps_per_sync=0, mlp_weights=None, stream=None, workspace=None,
                     out=None, return_stats=False, trace_capacity=0, profile=False, force_choice=None,
-                    single_round=False, return_rounds=False, multi_round=False):
+                    single_round=False, return_rounds=False, multi_round=False, relabel=True):
     """Trussness (int32, >= 2) of every edge of a simple undirected CSR graph, on the GPU.
 
     offsets: int64 (or int32) [n+1]; adj: int32 [2m]; numpy arrays (copied to the GPU) or
     CUDA tensors.  Returns a CUDA int32 tensor [m] (and a stats dict if return_stats; with
     trace_capacity > 0 the stats dict also holds the per-sequence trace of the peeling loop).
     With return_rounds, also the frontier round that processed every edge (int32 [m], a
-    peeling order), right after the trussness.
+    peeling order), right after the trussness.  relabel (default) decomposes the graph
+    relabelled by increasing degree and maps the result back (same output, faster).
     """
     torch = _torch()
     lib = load()
@@ -306,7 +309,7 @@ def truss_decompose(offsets, adj, *, variant="auto", device_loop="pipelined", va
     two_m = adj_t.numel()
     m = two_m // 2
     opt = make_options(variant, device_loop, validate, owner_rule, compact, steps_per_sync, mlp_weights, profile,
-                       force_choice, single_round, multi_round)
+                       force_choice, single_round, multi_round, relabel)
     if workspace is None:
         nb = workspace_bytes(n, two_m, opt) + (8 * (n + 1) + 256 if off32 else 0)
         _buf, wptr = alloc_workspace(nb)

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpkt.so")
-SOURCES = ["api.hip", "truss.hip", "peel.hip", "batched.hip", "persist.hip", "mlp.hip", "ktruss.hip", "kcore.hip",
+SOURCES = ["api.hip", "truss.hip", "peel.hip", "batched.hip", "persist.hip", "relabel.hip", "mlp.hip", "ktruss.hip", "kcore.hip",
            "kco.hip", "hindex.hip"]
 
 HIPCC_FLAGS = [

@@ -26,6 +26,9 @@ truss_status run_single(const Work& w, const truss_options& opt, truss_stats* st
                         hipStream_t s, bool support_only);
 truss_status prepare_off64(Work& w, const i32* off32, hipStream_t s);
 truss_status run_edge_list(const Work& w, i32* el_u, i32* el_v, hipStream_t s);
+size_t relabel_workspace_bytes(i32 n, i64 two_m);
+truss_status run_relabelled(i32 n, i64 two_m, const i64* off64_in, const i32* off32_in, const i32* adj, i32* out,
+                            void* ws, const truss_options& opt, truss_stats* stats, hipStream_t s);
 
 static truss_status check_options(const truss_options* o) {
   if (o->variant < TRUSS_VARIANT_AUTO || o->variant > TRUSS_VARIANT_LEARNED) {
@@ -38,6 +41,10 @@ static truss_status check_options(const truss_options* o) {
   }
   if (o->device_loop < 0 || o->device_loop > 3) {
     set_error("device_loop must be 0 (host), 1 (device), 2 (device, hipGraph) or 3 (pipelined host)");
+    return TRUSS_E_ARG;
+  }
+  if (o->relabel != 0 && o->relabel != 1) {
+    set_error("relabel must be 0 or 1");
     return TRUSS_E_ARG;
   }
   if (o->steps_per_sync < 0) {
@@ -96,11 +103,15 @@ static truss_status decompose_common(i32 n, const OffT* offsets, const i32* adj,
     return TRUSS_E_ARG;
   }
   const bool off32 = sizeof(OffT) == 4;
-  const size_t need = work_layout(n, two_m, off32, nullptr, nullptr);
+  const bool relabel = opt.relabel && !support_only && two_m > 0;
+  const size_t need = relabel ? relabel_workspace_bytes(n, two_m) : work_layout(n, two_m, off32, nullptr, nullptr);
   if (ws == nullptr || ws_bytes < need || ((uintptr_t)ws & 255u)) {
     set_error("workspace: need %zu bytes at 256-byte alignment, got %zu at %p", need, ws_bytes, ws);
     return TRUSS_E_WORKSPACE;
   }
+  if (relabel)
+    return run_relabelled(n, two_m, off32 ? nullptr : (const i64*)offsets, off32 ? (const i32*)offsets : nullptr,
+                          adj, out, ws, opt, stats, s);
   Work w;
   work_layout(n, two_m, off32, ws, &w);
   w.adj = adj;
@@ -217,10 +228,10 @@ void truss_default_options(truss_options* opt) {
   opt->batch_mode = 0;
   opt->force_choice = 0;
   opt->single_round = 0;
+  opt->relabel = 1;
 }
 
 truss_status truss_workspace_bytes(int32_t n, int64_t two_m, const truss_options* opt, size_t* bytes) {
-  (void)opt;
   if (n < 0 || two_m < 0 || (two_m & 1) || bytes == nullptr) {
     set_error("bad arguments to truss_workspace_bytes");
     return TRUSS_E_ARG;
@@ -229,7 +240,12 @@ truss_status truss_workspace_bytes(int32_t n, int64_t two_m, const truss_options
     set_error("m exceeds 2^31 - 1");
     return TRUSS_E_RANGE;
   }
-  *bytes = work_layout(n, two_m, true, nullptr, nullptr);
+  size_t need = work_layout(n, two_m, true, nullptr, nullptr);
+  if (opt == nullptr || opt->relabel) {
+    const size_t r = relabel_workspace_bytes(n, two_m);
+    if (r > need) need = r;
+  }
+  *bytes = need;
   return TRUSS_OK;
 }
 

@@ -429,6 +429,64 @@ bool ws_ok(void* ws, size_t bytes, size_t need) {
 
 }  // namespace
 
+namespace pkt {
+
+// Order and relabelled CSR for the library's own use (truss_decompose's relabelling):
+// the inputs are known good (validated CSR, non-negative keys below 2^key_bits), so
+// nothing is checked and nothing waits on the host.  The scratch (kco_scratch_bytes)
+// is free again on return.
+size_t kco_scratch_bytes(i32 n, i64 two_m) {
+  const size_t a = ko_layout(n, nullptr, nullptr, nullptr), b = rl_layout(two_m, nullptr, nullptr, nullptr);
+  return a > b ? a : b;
+}
+
+// new_id / order by increasing (keys[v], v).
+truss_status kco_order_run(i32 n, const i32* keys, int key_bits, i32* new_id, i32* order, void* scratch,
+                           hipStream_t s) {
+  if (n == 0) return TRUSS_OK;
+  RsBufs b;
+  KoFlags* fl;
+  ko_layout(n, scratch, &b, &fl);
+  PKT_HIP(hipMemsetAsync(fl, 0, sizeof(KoFlags), s));
+  PKT_HIP(hipMemsetAsync(b.arrive, 0, sizeof(u32), s));
+  hipLaunchKernelGGL(k_ko_init, dim3(grid_items(n)), dim3(PKT_BLOCK), 0, s, n, keys, b.k[0], b.v[0], fl);
+  PKT_LAUNCH_CHECK();
+  int q = 0;
+  if (truss_status st = rs_sort(n, key_bits, b, s, &q)) return st;
+  hipLaunchKernelGGL(k_ko_out, dim3(grid_items(n)), dim3(PKT_BLOCK), 0, s, n, (const i32*)b.v[q], order, new_id, fl);
+  PKT_LAUNCH_CHECK();
+  return TRUSS_OK;
+}
+
+// The relabelled CSR (rows sorted) of a valid symmetric CSR.
+truss_status kco_relabel_run(i32 n, i64 two_m, const i64* off, const i32* adj, const i32* new_id, const i32* order,
+                             i64* off2, i32* adj2, void* scratch, hipStream_t s) {
+  const i64 max_slots = (((i64)1 << 24) - 1) * RS_TILE;  // the radix sort's launch limit
+  if (two_m > max_slots) {
+    set_error("relabelling: %lld adjacency slots, above the radix sort's %lld", (long long)two_m,
+              (long long)max_slots);
+    return TRUSS_E_RANGE;
+  }
+  RsBufs b;
+  KoFlags* fl;
+  rl_layout(two_m, scratch, &b, &fl);
+  PKT_HIP(hipMemsetAsync(fl, 0, sizeof(KoFlags), s));
+  PKT_HIP(hipMemsetAsync(b.arrive, 0, sizeof(u32), s));
+  PKT_HIP(scan_launch(RelabelRows{order, off, n}, b.partial, off2, b.arrive, s));
+  if (two_m == 0) return TRUSS_OK;
+  hipLaunchKernelGGL(k_rl_pairs, dim3(grid_items(two_m)), dim3(PKT_BLOCK), 0, s, n, two_m, off, adj, new_id,
+                     (const i64*)off2, b.k[0], b.v[0], fl);
+  PKT_LAUNCH_CHECK();
+  int q = 0;
+  if (truss_status st = rs_sort(two_m, bit_width((i64)n - 1), b, s, &q)) return st;
+  PKT_HIP(hipMemcpyAsync(adj2, b.v[q], sizeof(i32) * (size_t)two_m, hipMemcpyDeviceToDevice, s));
+  return TRUSS_OK;
+}
+
+int kco_bits(i64 x) { return bit_width(x); }
+
+}  // namespace pkt
+
 extern "C" truss_status truss_kco_order_workspace_bytes(int32_t n, size_t* bytes) {
   pkt::set_error("");
   if (n < 0 || bytes == nullptr) {

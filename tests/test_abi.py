@@ -62,7 +62,7 @@ def test_default_options_and_struct_sizes(lib):
 
     o = pkt.default_options()
     assert (o.variant, o.device_loop, o.validate, o.owner_rule, o.compact) == (0, 3, 1, 0, 1)
-    assert o.batch_mode == 0 and o.multi_round == 0 and list(o.reserved) == [0] * 7
+    assert o.batch_mode == 0 and o.multi_round == 0 and o.relabel == 1 and list(o.reserved) == [0] * 6
     assert ctypes.sizeof(pkt.Options) == 96
     assert ctypes.sizeof(pkt.Stats) == 160
     assert ctypes.sizeof(pkt.TraceRecord) == 72

@@ -122,6 +122,10 @@ def test_support_and_edge_list(gpu_lib, make):
     dict(device_loop="host", force_choice="hash"),
     dict(device_loop="graph", force_choice="hash"),
     dict(multi_round=True, variant="merge"),
+    dict(relabel=False),
+    dict(relabel=False, device_loop="host"),
+    dict(relabel=False, force_choice="wave"),
+    dict(relabel=False, device_loop="graph", compact=False),
 ])
 def test_medium_graphs(gpu_lib, make, opts):
     g = make()
@@ -129,10 +133,34 @@ def test_medium_graphs(gpu_lib, make, opts):
     assert np.array_equal(gpu_tau(gpu_lib, g, **opts), oracle.truss(g))
 
 
-def test_int32_offsets(gpu_lib):
+@pytest.mark.parametrize("relabel", [True, False])
+def test_int32_offsets(gpu_lib, relabel):
     g = gg.rmat(11, 16, seed=2)
-    tau = gpu_lib.truss_decompose(g.offsets.astype(np.int32), g.adj).cpu().numpy()
+    tau = gpu_lib.truss_decompose(g.offsets.astype(np.int32), g.adj, relabel=relabel).cpu().numpy()
     assert np.array_equal(tau, oracle.truss(g))
+
+
+def test_relabel_workspace_and_phase_times(gpu_lib):
+    """The relabelling needs its larger workspace (refused below it) and reports its
+    time inside the build phase; without it the smaller workspace is enough."""
+    import torch
+
+    g = gg.rmat(12, 16, seed=4)
+    n, two_m = g.n, len(g.adj)
+    small = gpu_lib.workspace_bytes(n, two_m, gpu_lib.make_options(relabel=False))
+    big = gpu_lib.workspace_bytes(n, two_m)
+    assert big > small
+    off, adj = torch.from_numpy(g.offsets).cuda(), torch.from_numpy(g.adj).cuda()
+    buf, ptr = gpu_lib.alloc_workspace(small)
+    ws = gpu_lib.Workspace(n, two_m, buf, ptr, small)
+    with pytest.raises(gpu_lib.TrussError) as ei:
+        gpu_lib.truss_decompose(off, adj, workspace=ws)
+    assert ei.value.name == "TRUSS_E_WORKSPACE"
+    want = oracle.truss(g)
+    assert np.array_equal(gpu_lib.truss_decompose(off, adj, workspace=ws, relabel=False).cpu().numpy(), want)
+    tau, st = gpu_lib.truss_decompose(off, adj, return_stats=True)
+    assert np.array_equal(tau.cpu().numpy(), want)
+    assert st["ms_build"] > 0 and st["ms_total"] >= st["ms_build"] + st["ms_peel"]
 
 
 def test_repeatable(gpu_lib):
@@ -281,6 +309,7 @@ def test_full_size_against_stored_oracle(gpu_lib, name):
     dict(force_choice="wave"),
     dict(force_choice="hash"),
     dict(multi_round=True),
+    dict(relabel=False),
 ])
 def test_full_size_variants_rmat20(gpu_lib, opts):
     """Launch variants and loop drivers at the full R-MAT scale-20 size: every one gives
@@ -346,11 +375,12 @@ def test_batch_every_graph_against_stored_oracle(gpu_lib, name, mode, variant):
     lambda: gg.rmat(13, 16, seed=5),
     lambda: gg.chunglu(1 << 12, 2.1, 3.0e4, draws=27_000, ncliques=4, cmin=10, cmax=40, seed=6),
 ])
-@pytest.mark.parametrize("mode", ["pipelined", "host"])
-def test_rounds_are_a_peeling_certificate(gpu_lib, make, mode):
+@pytest.mark.parametrize("mode,relabel", [("pipelined", True), ("host", True), ("pipelined", False)])
+def test_rounds_are_a_peeling_certificate(gpu_lib, make, mode, relabel):
     g = make()
-    say("case", g.name, mode)
-    tau, rounds = gpu_lib.truss_decompose(g.offsets, g.adj, device_loop=mode, return_rounds=True)
+    say("case", g.name, mode, "relabel", relabel)
+    tau, rounds = gpu_lib.truss_decompose(g.offsets, g.adj, device_loop=mode, return_rounds=True,
+                                          relabel=relabel)
     tau, rounds = tau.cpu().numpy(), rounds.cpu().numpy()
     assert np.array_equal(tau, oracle.truss(g))
     res = certificate.verify(g, tau, rounds)
