@@ -2,8 +2,9 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rmat20]
 
-A step is one whole truss decomposition (edge ids, orientation, support, every
-level scan and sub-level, output) of one synthetic graph that is already resident
+A step is one whole truss decomposition (the degree-order relabelling, edge ids,
+orientation, support, every level scan and sub-level, the map back to the input's
+edge order) of one synthetic graph that is already resident
 in device memory, through the library's C ABI with input validation off (the input
 is validated once, outside the timed region, and the result is checked against the
 stored oracle expectation when one exists).  Prints one JSON line.
@@ -56,7 +57,7 @@ def measured_traffic(workload):
     fields = dict(l.split(" = ", 1) for l in open(path).read().splitlines() if " = " in l)
     csrc = os.path.join(ROOT, "paper_1707_02000_amd", "csrc")
     src = "".join(open(os.path.join(csrc, f)).read()
-                  for f in ("common.h", "truss.h", "peel.h", "scan.h", "psl.h", "peel.hip"))
+                  for f in ("common.h", "truss.h", "peel.h", "scan.h", "psl.h", "peel.hip", "relabel.hip", "kco.hip"))
     if hashlib.sha256(src.encode()).hexdigest()[:16] != fields.get("source_sha256_16", "").strip():
         return None
     return float(fields["traffic_bytes_per_launch"])
@@ -151,6 +152,10 @@ def extras(pkt, torch, gg, off20, adj20, m20, ms20, steps):
     from paper_1707_02000_amd import tuner
 
     out = {}
+    # the main line without the library's degree-order relabelling (same output)
+    t = _timed(lambda: pkt.truss_decompose(off20, adj20, validate=False, relabel=False), steps, 1, torch)
+    out["no_relabel_rmat20"] = {"ms_per_step": round(t * 1e3, 2), "value": m20 / t, "relabel_gain": t * 1e3 / ms20}
+    print(f"bench: rmat20 without relabelling {t * 1e3:.1f} ms", file=sys.stderr, flush=True)
     # the level loop's drivers on the same graph (pipelined is the main line's)
     drivers = {}
     for mode in ("host", "device", "graph", "pipelined"):
@@ -183,8 +188,8 @@ def extras(pkt, torch, gg, off20, adj20, m20, ms20, steps):
     nid, order = pkt.kco_order(core20)
     tr = _timed(lambda: pkt.kco_relabel(off20, adj20, nid, order), 3, 1, torch)
     off2, adj2 = pkt.kco_relabel(off20, adj20, nid, order)
-    td = _timed(lambda: pkt.truss_decompose(off2, adj2, validate=False), 2, 1, torch)
-    tau2 = pkt.truss_decompose(off2, adj2, validate=False)
+    td = _timed(lambda: pkt.truss_decompose(off2, adj2, validate=False, relabel=False), 2, 1, torch)
+    tau2 = pkt.truss_decompose(off2, adj2, validate=False, relabel=False)
     tm = _timed(lambda: pkt.kco_map(n20, el20, nid, off2, adj2, tau2), 3, 1, torch)
     same = bool(torch.equal(pkt.kco_map(n20, el20, nid, off2, adj2, tau2), tau20))
     out["kco_rmat20"] = {"order_ms": round(to * 1e3, 3), "relabel_ms": round(tr * 1e3, 3),
@@ -220,6 +225,8 @@ def extras(pkt, torch, gg, off20, adj20, m20, ms20, steps):
         tp = _timed(lambda: pkt.truss_decompose(off, adj, validate=False, workspace=ws, out=o), reps, 1, torch)
         tl = _timed(lambda: pkt.truss_decompose(off, adj, validate=False, workspace=ws, out=o, variant="learned",
                                                 mlp_weights=W), reps, 1, torch)
+        tn = _timed(lambda: pkt.truss_decompose(off, adj, validate=False, workspace=ws, out=o, relabel=False),
+                    reps, 1, torch)
         same = bool(torch.equal(o[:g.m], ref[:g.m]))
         gold = os.path.join(ROOT, "tests", "golden", f"{name}.json")
         parity = None
@@ -228,8 +235,10 @@ def extras(pkt, torch, gg, off20, adj20, m20, ms20, steps):
             parity = rec["csr_sha256"] == g.sha256() and rec["trussness_sha256"] == sha(ref[:g.m].cpu().numpy())
         out[name] = {"m": g.m, "value": g.m / tp, "ms_per_step": tp * 1e3, "t_max": st["t_max"],
                      "levels": st["levels"], "sublevels": st["sublevels"], "parity_vs_oracle": parity,
-                     "learned_value": g.m / tl, "learned_vs_plain": tp / tl, "learned_bit_identical": same}
-        print(f"bench: {name} plain {tp * 1e3:.1f} ms learned {tl * 1e3:.1f} ms parity {parity}", file=sys.stderr,
+                     "learned_value": g.m / tl, "learned_vs_plain": tp / tl, "learned_bit_identical": same,
+                     "no_relabel_ms_per_step": tn * 1e3, "relabel_gain": tn / tp}
+        print(f"bench: {name} plain {tp * 1e3:.1f} ms learned {tl * 1e3:.1f} ms no relabel {tn * 1e3:.1f} ms "
+              f"parity {parity}", file=sys.stderr,
               flush=True)
         del off, adj, ws, o, ref
         torch.cuda.empty_cache()
@@ -377,7 +386,7 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload], "n": g.n, "m": g.m,
-                   "variant": args.variant, "loop": args.loop},
+                   "variant": args.variant, "loop": args.loop, "relabel": "auto (degree order)"},
         "parity_vs_oracle": parity,
         "wedges_per_s": pkt.wedges(deg) / (ms / 1000.0),
         "t_max": st0["t_max"],

@@ -124,6 +124,11 @@ typedef struct {
   truss_trace_record* records;
 } truss_trace;
 
+/* truss_options.relabel = 1 (auto) relabels graphs of at least this many edges ... */
+#define TRUSS_RELABEL_MIN_EDGES (1 << 20)
+/* ... whose maximum degree is at least this many times the mean degree 2m / n. */
+#define TRUSS_RELABEL_MIN_SKEW 16
+
 typedef struct {
   int32_t variant;           /* truss_variant; default AUTO */
   int32_t device_loop;       /* 0 = host-driven: the host reads the loop state after every launch
@@ -162,13 +167,18 @@ typedef struct {
                                 cooperative launch of 64 workgroups that meet at a grid barrier
                                 between rounds (measured slower than one launch per round on
                                 this GPU; default 0) */
-  int32_t relabel;           /* 1 = truss_decompose and truss_decompose32 relabel the vertices by
-                                increasing (degree, id) on the device, decompose the relabelled
-                                graph and map its trussness (and peel_round) back to the input's
-                                edge order (default 1): the output does not change, the level loop
-                                runs faster because the high-degree rows it searches most sit
-                                together.  Needs the larger workspace truss_workspace_bytes gives
-                                for it; its time is counted in ms_build.  Not used by
+  int32_t relabel;           /* truss_decompose and truss_decompose32 only: 0 = decompose the graph
+                                as given; 2 = relabel the vertices by increasing (degree, id) on the
+                                device, decompose the relabelled graph and map its trussness (and
+                                peel_round) back to the input's edge order -- the output does not
+                                change, and on graphs with hubs the level loop runs faster because
+                                the high-degree rows it searches most sit together; 1 = auto
+                                (default): relabel when the graph has at least
+                                TRUSS_RELABEL_MIN_EDGES edges and a maximum degree at least
+                                TRUSS_RELABEL_MIN_SKEW times the mean degree (where it was measured
+                                to gain; small or evenly spread graphs lose its cost).  1 and 2
+                                need the larger workspace truss_workspace_bytes gives for them; the
+                                relabelling's time is counted in ms_build.  Not used by
                                 truss_support, truss_decompose32_static or the batched entry
                                 point */
   int32_t reserved[6];       /* zero (room for later options without a layout change) */
@@ -203,9 +213,9 @@ void truss_default_options(truss_options* opt);
 
 /* Workspace bytes needed by truss_decompose and truss_decompose32 for a graph with
  * n vertices and two_m adjacency slots (= offsets[n]) under the options *opt (NULL =
- * defaults).  With relabel = 1 (the default) this adds, beyond the decomposition's
- * own arrays, the relabelled CSR and the permutation: about 16 bytes per edge and
- * 40 per vertex more. */
+ * defaults).  With relabel = 1 or 2 (the default is 1) this adds, beyond the
+ * decomposition's own arrays, the relabelled CSR and the permutation: about 16 bytes
+ * per edge and 40 per vertex more. */
 truss_status truss_workspace_bytes(int32_t n, int64_t two_m, const truss_options* opt, size_t* bytes);
 
 /*

@@ -206,7 +206,7 @@ def default_options() -> Options:
 
 def make_options(variant="auto", device_loop="pipelined", validate=True, owner_rule=0, compact=True,
                  steps_per_sync=0, mlp_weights=None, profile=False, force_choice=None,
-                 single_round=False, multi_round=False, relabel=True) -> Options:
+                 single_round=False, multi_round=False, relabel="auto") -> Options:
     o = default_options()
     o.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
     o.device_loop = loop_mode(device_loop)
@@ -221,8 +221,20 @@ def make_options(variant="auto", device_loop="pipelined", validate=True, owner_r
         o.force_choice = CHOICES.index(force_choice) if isinstance(force_choice, str) else int(force_choice)
     o.single_round = int(bool(single_round))
     o.multi_round = int(bool(multi_round))
-    o.relabel = int(bool(relabel))
+    o.relabel = relabel_mode(relabel)
     return o
+
+
+RELABEL = {"off": 0, "auto": 1, "always": 2}
+
+
+def relabel_mode(x) -> int:
+    """truss_options.relabel from "off" / "auto" / "always", False (off) or True (always)."""
+    if isinstance(x, str):
+        return RELABEL[x]
+    if isinstance(x, bool):
+        return 2 if x else 0
+    return int(x)
 
 
 def _torch():
@@ -289,15 +301,16 @@ class Workspace:
 def truss_decompose(offsets, adj, *, variant="auto", device_loop="pipelined", validate=True, owner_rule=0,
                     compact=True, steps_per_sync=0, mlp_weights=None, stream=None, workspace=None,
                     out=None, return_stats=False, trace_capacity=0, profile=False, force_choice=None,
-                    single_round=False, return_rounds=False, multi_round=False, relabel=True):
+                    single_round=False, return_rounds=False, multi_round=False, relabel="auto"):
     """Trussness (int32, >= 2) of every edge of a simple undirected CSR graph, on the GPU.
 
     offsets: int64 (or int32) [n+1]; adj: int32 [2m]; numpy arrays (copied to the GPU) or
     CUDA tensors.  Returns a CUDA int32 tensor [m] (and a stats dict if return_stats; with
     trace_capacity > 0 the stats dict also holds the per-sequence trace of the peeling loop).
     With return_rounds, also the frontier round that processed every edge (int32 [m], a
-    peeling order), right after the trussness.  relabel (default) decomposes the graph
-    relabelled by increasing degree and maps the result back (same output, faster).
+    peeling order), right after the trussness.  relabel: "auto" (default) decomposes large
+    graphs with skewed degrees relabelled by increasing degree and maps the result back (same
+    output, faster there); True / "always" does so for every graph, False / "off" never.
     """
     torch = _torch()
     lib = load()

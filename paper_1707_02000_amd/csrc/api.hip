@@ -43,8 +43,8 @@ static truss_status check_options(const truss_options* o) {
     set_error("device_loop must be 0 (host), 1 (device), 2 (device, hipGraph) or 3 (pipelined host)");
     return TRUSS_E_ARG;
   }
-  if (o->relabel != 0 && o->relabel != 1) {
-    set_error("relabel must be 0 or 1");
+  if (o->relabel < 0 || o->relabel > 2) {
+    set_error("relabel must be 0 (off), 1 (auto) or 2 (always)");
     return TRUSS_E_ARG;
   }
   if (o->steps_per_sync < 0) {
@@ -103,8 +103,13 @@ static truss_status decompose_common(i32 n, const OffT* offsets, const i32* adj,
     return TRUSS_E_ARG;
   }
   const bool off32 = sizeof(OffT) == 4;
-  const bool relabel = opt.relabel && !support_only && two_m > 0;
-  const size_t need = relabel ? relabel_workspace_bytes(n, two_m) : work_layout(n, two_m, off32, nullptr, nullptr);
+  // the workspace truss_workspace_bytes gives for these options; relabel = 1 (auto) leaves
+  // graphs below TRUSS_RELABEL_MIN_EDGES edges as they are
+  const bool relabel_ws = opt.relabel != 0 && !support_only && two_m > 0;
+  const bool relabel =
+      relabel_ws && (opt.relabel == 2 || two_m / 2 >= (i64)TRUSS_RELABEL_MIN_EDGES);
+  const size_t need =
+      relabel_ws ? relabel_workspace_bytes(n, two_m) : work_layout(n, two_m, off32, nullptr, nullptr);
   if (ws == nullptr || ws_bytes < need || ((uintptr_t)ws & 255u)) {
     set_error("workspace: need %zu bytes at 256-byte alignment, got %zu at %p", need, ws_bytes, ws);
     return TRUSS_E_WORKSPACE;

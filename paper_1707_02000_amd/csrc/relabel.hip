@@ -9,12 +9,15 @@
 // sit together at the top of the id range, their rows and support words in a few
 // places of memory.  Steps, all on the stream:
 //   1. validate the input CSR (when asked), copy int32 offsets to int64;
-//   2. new ids: a stable radix sort of (degree, id); the relabelled CSR, rows sorted;
-//   3. decompose the relabelled graph (edge ids, support, level loop);
-//   4. for every edge (a, b) of the relabelled graph, the input edge (order[a],
-//      order[b]) and its canonical id (the upper entries of the rows before its
-//      smaller endpoint, then its rank in that row): trussness (and the round, when
-//      a peeling order is asked for) scattered there.
+//   2. degrees and their maximum: under the automatic policy (which sends graphs below
+//      TRUSS_RELABEL_MIN_EDGES edges elsewhere), a graph whose maximum degree is below
+//      TRUSS_RELABEL_MIN_SKEW times the mean is decomposed as given from here;
+//   3. new ids: a stable radix sort of (degree, id); the relabelled CSR, rows sorted;
+//   4. decompose the relabelled graph (edge ids, support, level loop);
+//   5. for every input edge (x, y), x < y, in input edge order: its image {new_id[x],
+//      new_id[y]} located in the relabelled row of the lower-degree endpoint, whose
+//      slot gives the relabelled edge id; its trussness (and round, when a peeling
+//      order is asked for) gathered from there.
 // Workspace: region A (the decomposition's own layout, which the order and relabel
 // steps use as scratch before the decomposition starts), then the relabelled CSR,
 // the permutation and the map's arrays.
@@ -47,9 +50,17 @@ inline int grid_r(i64 count, int cap = 8192) {
   return (int)g;
 }
 
-__global__ __launch_bounds__(PKT_BLOCK) void k_degree(i32 n, const i64* __restrict__ off, i32* __restrict__ deg) {
-  for (i64 v = (i64)blockIdx.x * PKT_BLOCK + threadIdx.x; v < n; v += (i64)gridDim.x * PKT_BLOCK)
-    deg[v] = (i32)(off[v + 1] - off[v]);
+// Degrees (the sort key) and their maximum (atomicMax of every wave's maximum).
+__global__ __launch_bounds__(PKT_BLOCK) void k_degree(i32 n, const i64* __restrict__ off, i32* __restrict__ deg,
+                                                     u32* __restrict__ dmax) {
+  u32 mx = 0;
+  for (i64 v = (i64)blockIdx.x * PKT_BLOCK + threadIdx.x; v < n; v += (i64)gridDim.x * PKT_BLOCK) {
+    const i32 d = (i32)(off[v + 1] - off[v]);
+    deg[v] = d;
+    mx = max(mx, (u32)d);
+  }
+  for (int o = PKT_WAVE / 2; o >= 1; o >>= 1) mx = max(mx, (u32)__shfl_xor((int)mx, o));
+  if (lane_id() == 0 && mx > 0) atomicMax(dmax, mx);
 }
 
 // First slot of input row x above x: the row's canonical edges run from there.
@@ -68,24 +79,43 @@ struct UpperLen {
   __device__ i64 len(i64 x) const { return off[x + 1] - us[x]; }
 };
 
-// Relabelled edge e2 = (a, b) is the input edge (order[a], order[b]); its canonical
-// id is eb[x] + (rank of y among x's entries above x), x < y its endpoints.
-__global__ __launch_bounds__(PKT_BLOCK) void k_map_back(i64 m, const int2* __restrict__ el2,
-                                                       const i32* __restrict__ order, const i64* __restrict__ off,
+// Input slot j of row x with y = adj[j] above x holds the input edge e = eb[x] + (j - us[x]).
+// Its image is the relabelled edge {new_id[x], new_id[y]}, found in the relabelled row of the
+// smaller new id -- the endpoint of lower degree, so a short row -- whose slot carries the
+// relabelled edge id.  A block takes PKT_BLOCK consecutive slots at a time and finds the
+// rows of its first and last slot once; the output is written in input edge order.
+__global__ __launch_bounds__(PKT_BLOCK) void k_map_back(i32 n, i64 two_m, const i64* __restrict__ off,
                                                        const i32* __restrict__ adj, const i64* __restrict__ us,
-                                                       const i64* __restrict__ eb, const i32* __restrict__ tau2,
+                                                       const i64* __restrict__ eb, const i32* __restrict__ new_id,
+                                                       const i64* __restrict__ off2, const i32* __restrict__ adj2,
+                                                       const i32* __restrict__ eid2, const i32* __restrict__ tau2,
                                                        i32* __restrict__ tau, const i32* __restrict__ rounds2,
                                                        i32* __restrict__ rounds) {
-  for (i64 e2 = (i64)blockIdx.x * PKT_BLOCK + threadIdx.x; e2 < m; e2 += (i64)gridDim.x * PKT_BLOCK) {
-    const int2 ab = el2[e2];
-    const i32 u = order[ab.x], v = order[ab.y];
-    const i32 x = min(u, v), y = max(u, v);
-    const i64 b = us[x], end = off[x + 1];
-    const i64 pos = lower_bound_dev(adj, b, end, y);
-    const i64 e = eb[x] + (pos - b);
-    if (e < 0 || e >= m) continue;  // only for a CSR outside the contract (validation off)
-    tau[e] = tau2[e2];
-    if (rounds) rounds[e] = rounds2[e2];
+  __shared__ i64 rows[2];
+  const i64 m = two_m / 2;
+  for (i64 base = (i64)blockIdx.x * PKT_BLOCK; base < two_m; base += (i64)gridDim.x * PKT_BLOCK) {
+    const i64 last = min(base + PKT_BLOCK, two_m) - 1;
+    if (threadIdx.x == 0) rows[0] = upper_bound_dev(off, (i64)0, (i64)n + 1, base) - 1;
+    if (threadIdx.x == PKT_WAVE) rows[1] = upper_bound_dev(off, (i64)0, (i64)n + 1, last) - 1;
+    __syncthreads();
+    const i64 j = base + threadIdx.x;
+    if (j < two_m) {
+      const i32 x = (i32)(upper_bound_dev(off, rows[0], rows[1] + 1, j) - 1);
+      const i32 y = adj[j];
+      if (y > x) {
+        const i32 a = new_id[x], b = new_id[y];
+        const i32 lo = min(a, b), hi = max(a, b);
+        const i64 rb = off2[lo], re = off2[lo + 1];
+        const i64 q = lower_bound_dev(adj2, rb, re, hi);
+        const i64 e = eb[x] + (j - us[x]);
+        if (q < re && adj2[q] == hi && e >= 0 && e < m) {  // always, for a CSR within the contract
+          const i32 e2 = eid2[q];
+          tau[e] = tau2[e2];
+          if (rounds) rounds[e] = rounds2[e2];
+        }
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -103,6 +133,7 @@ struct RelabelWork {
   i64* eb;        // [n+1] first canonical edge id of every input row
   i64* partial;   // [SCAN_BLOCKS + 1]
   u32* arrive;
+  u32* dmax;      // maximum degree
 };
 
 size_t relabel_layout(i32 n, i64 two_m, void* ws, RelabelWork* r) {
@@ -122,6 +153,7 @@ size_t relabel_layout(i32 n, i64 two_m, void* ws, RelabelWork* r) {
   t.eb = cv.take<i64>((size_t)n + 1);
   t.partial = cv.take<i64>(SCAN_BLOCKS + 1);
   t.arrive = cv.take<u32>(1);
+  t.dmax = cv.take<u32>(1);
   if (r) *r = t;
   return cv.used;
 }
@@ -170,15 +202,36 @@ truss_status run_relabelled(i32 n, i64 two_m, const i64* off64_in, const i32* of
     if (st) return st;
   }
   if (timed) PKT_HIP(hipEventRecord(ev[1], s));
-  // 2. new ids by increasing (degree, id), the relabelled CSR
-  hipLaunchKernelGGL(k_degree, dim3(grid_r(n)), dim3(PKT_BLOCK), 0, s, n, off, r.key);
+  // 2. degrees; with relabel = 1, the graph as given unless its degrees are skewed (the
+  // caller has checked its size)
+  PKT_HIP(hipMemsetAsync(r.dmax, 0, sizeof(u32), s));
+  hipLaunchKernelGGL(k_degree, dim3(grid_r(n)), dim3(PKT_BLOCK), 0, s, n, off, r.key, r.dmax);
   PKT_LAUNCH_CHECK();
+  if (opt.relabel == 1) {
+    u32 dmax = 0;
+    PKT_HIP(hipMemcpyAsync(&dmax, r.dmax, sizeof(u32), hipMemcpyDeviceToHost, s));
+    PKT_HIP(hipStreamSynchronize(s));
+    if ((i64)dmax * (i64)n < (i64)TRUSS_RELABEL_MIN_SKEW * two_m) {  // dmax below skew x (2m / n)
+      truss_options o1 = opt;
+      o1.validate = 0;  // done above
+      truss_status st = run_single(wv, o1, stats, out, s, false);
+      if (st) return st;
+      if (timed) {
+        float t_val = 0.f;
+        PKT_HIP(hipEventElapsedTime(&t_val, ev[0], ev[1]));
+        stats->ms_validate += t_val;
+        stats->ms_total += t_val;
+      }
+      return TRUSS_OK;
+    }
+  }
+  // 3. new ids by increasing (degree, id), the relabelled CSR
   truss_status st = kco_order_run(n, r.key, kco_bits((i64)n - 1), r.new_id, r.order, r.regionA, s);
   if (st) return st;
   st = kco_relabel_run(n, two_m, off, adj, r.new_id, r.order, r.off2, r.adj2, r.regionA, s);
   if (st) return st;
   if (timed) PKT_HIP(hipEventRecord(ev[2], s));
-  // 3. the decomposition of the relabelled graph
+  // 4. the decomposition of the relabelled graph
   Work w2;
   work_layout(n, two_m, false, r.regionA, &w2);
   w2.off = r.off2;
@@ -190,13 +243,13 @@ truss_status run_relabelled(i32 n, i64 two_m, const i64* off64_in, const i32* of
   st = run_single(w2, o2, stats, r.tau2, s, false);
   if (st) return st;
   if (timed) PKT_HIP(hipEventRecord(ev[3], s));
-  // 4. back to the input's edges
+  // 5. back to the input's edges
   PKT_HIP(hipMemsetAsync(r.arrive, 0, sizeof(u32), s));
   hipLaunchKernelGGL(k_upper_start, dim3(grid_r(n)), dim3(PKT_BLOCK), 0, s, n, off, adj, r.us);
   PKT_HIP(scan_launch(UpperLen{off, r.us, n}, r.partial, r.eb, r.arrive, s));
-  hipLaunchKernelGGL(k_map_back, dim3(grid_r(m)), dim3(PKT_BLOCK), 0, s, m, (const int2*)w2.el,
-                     (const i32*)r.order, off, adj, (const i64*)r.us, (const i64*)r.eb, (const i32*)r.tau2, out,
-                     (const i32*)r.rounds2, opt.peel_round);
+  hipLaunchKernelGGL(k_map_back, dim3(grid_r(two_m)), dim3(PKT_BLOCK), 0, s, n, two_m, off, adj, (const i64*)r.us,
+                     (const i64*)r.eb, (const i32*)r.new_id, (const i64*)r.off2, (const i32*)r.adj2,
+                     (const i32*)w2.eid, (const i32*)r.tau2, out, (const i32*)r.rounds2, opt.peel_round);
   PKT_LAUNCH_CHECK();
   if (timed) PKT_HIP(hipEventRecord(ev[4], s));
   PKT_HIP(hipStreamSynchronize(s));

@@ -62,6 +62,7 @@ def test_small_graphs(gpu_lib, name, g):
     assert np.array_equal(gpu_tau(gpu_lib, g), want)
     assert np.array_equal(gpu_tau(gpu_lib, g, force_choice="wave"), want)
     assert np.array_equal(gpu_tau(gpu_lib, g, force_choice="hash"), want)
+    assert np.array_equal(gpu_tau(gpu_lib, g, relabel=True), want)
 
 
 @pytest.mark.parametrize("make", [
@@ -122,6 +123,10 @@ def test_support_and_edge_list(gpu_lib, make):
     dict(device_loop="host", force_choice="hash"),
     dict(device_loop="graph", force_choice="hash"),
     dict(multi_round=True, variant="merge"),
+    dict(relabel=True),
+    dict(relabel=True, device_loop="host"),
+    dict(relabel=True, force_choice="wave", owner_rule=1),
+    dict(relabel=True, device_loop="graph", compact=False),
     dict(relabel=False),
     dict(relabel=False, device_loop="host"),
     dict(relabel=False, force_choice="wave"),
@@ -133,7 +138,7 @@ def test_medium_graphs(gpu_lib, make, opts):
     assert np.array_equal(gpu_tau(gpu_lib, g, **opts), oracle.truss(g))
 
 
-@pytest.mark.parametrize("relabel", [True, False])
+@pytest.mark.parametrize("relabel", [True, False, "auto"])
 def test_int32_offsets(gpu_lib, relabel):
     g = gg.rmat(11, 16, seed=2)
     tau = gpu_lib.truss_decompose(g.offsets.astype(np.int32), g.adj, relabel=relabel).cpu().numpy()
@@ -158,9 +163,30 @@ def test_relabel_workspace_and_phase_times(gpu_lib):
     assert ei.value.name == "TRUSS_E_WORKSPACE"
     want = oracle.truss(g)
     assert np.array_equal(gpu_lib.truss_decompose(off, adj, workspace=ws, relabel=False).cpu().numpy(), want)
-    tau, st = gpu_lib.truss_decompose(off, adj, return_stats=True)
+    tau, st = gpu_lib.truss_decompose(off, adj, return_stats=True, relabel=True)
     assert np.array_equal(tau.cpu().numpy(), want)
     assert st["ms_build"] > 0 and st["ms_total"] >= st["ms_build"] + st["ms_peel"]
+
+
+@pytest.mark.parametrize("make", [
+    lambda: gg.rgg(200_000, 30.0, seed=4),      # above the size limit, degrees not skewed: as given
+    lambda: gg.rmat(17, 16, seed=11),           # above it and skewed: relabelled
+    lambda: gg.er(90_000, mean_degree=24.0, seed=2),
+])
+def test_relabel_policies_agree(gpu_lib, make):
+    """The automatic policy on graphs above its size limit, on both sides of its skew test,
+    and the int32 entry point: every policy gives the trussness of the graph as given."""
+    import torch
+
+    g = make()
+    say("case", g.name, "m", g.m)
+    off, adj = torch.from_numpy(g.offsets).cuda(), torch.from_numpy(g.adj).cuda()
+    base = gpu_lib.truss_decompose(off, adj, relabel=False).cpu().numpy()
+    for mode in ("auto", "always"):
+        for o in (off, off.to(torch.int32)):
+            tau, rounds = gpu_lib.truss_decompose(o, adj, relabel=mode, return_rounds=True)
+            assert np.array_equal(tau.cpu().numpy(), base), mode
+            assert int(rounds.min()) >= 0
 
 
 def test_repeatable(gpu_lib):
