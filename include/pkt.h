@@ -91,7 +91,7 @@ typedef enum {
   TRUSS_VARIANT_FIXED = 3,   /* every round uses truss_options.force_choice (where valid) */
   TRUSS_VARIANT_LEARNED = 4  /* the MLP cost model (truss_options.mlp_weights) predicts the time
                                 of every valid choice from the frontier's features (frontiers of
-                                more than 2048 edges); the cheapest is launched when it is predicted
+                                more than 32768 edges); the cheapest is launched when it is predicted
                                 at least 10 % faster than the heuristic's launch, which stands
                                 otherwise and for smaller frontiers */
 } truss_variant;

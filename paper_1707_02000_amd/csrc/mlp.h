@@ -14,7 +14,9 @@
 // predicts the other launch at least 10 % faster: log2(1.1) in the model's units
 // (log2 microseconds).  Near the heuristic's threshold the two launches cost about
 // the same and the model's error would otherwise flip them back and forth.
+#ifndef MLP_MARGIN
 #define MLP_MARGIN 0.13750352f
+#endif
 
 #define MLP_IN 6
 #define MLP_H 64

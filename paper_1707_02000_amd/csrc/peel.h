@@ -47,10 +47,13 @@ __host__ __device__ __forceinline__ bool needs_compact(i64 alive, i64 csr_edges)
 #endif
 #define GALLOP_K 8           // shorter-row entries per item when galloping
 #define DECIDE_THREADS 512   // threads of the one-block kernel that picks a round's launch
-#define LEARNED_MIN_FRONTIER 2048  // the learned policy consults the model above this frontier size;
-                                   // smaller frontiers (most rounds) take the heuristic's fused launch:
-                                   // the features cost more there than a choice gains (per-round
-                                   // traces: R-MAT, Chung-Lu, batches)
+#ifndef LEARNED_MIN_FRONTIER
+#define LEARNED_MIN_FRONTIER 32768  // the learned policy consults the model above this frontier size;
+                                    // smaller frontiers (most rounds) take the heuristic's launch: the
+                                    // features and the forward pass cost more there than a choice gains
+                                    // (end to end on R-MAT s20-s24 and Chung-Lu 2^23, 2048 to 131072
+                                    // tried)
+#endif
 #define CHOICE_NONE (-1)     // Ctl::choice while no launch is picked for the current frontier
 
 // Loop state published by k_decide for the pipelined host loop, in host-mapped

@@ -164,7 +164,7 @@ def choose_batch(W, X, ncurr):
     return C.cpu().numpy(), Y.cpu().numpy()
 
 
-LEARNED_MIN_FRONTIER = 2048  # the library consults the model above this frontier size
+LEARNED_MIN_FRONTIER = 32768  # the library consults the model above this frontier size
 
 
 def learned_choices(W, rounds):
@@ -201,6 +201,29 @@ def _graph_for(name):
     return gg.workload(name, seed=1)
 
 
+def evaluate_weights(path, train, held_out, repeats=2, report_path=None):
+    """The learned policy of the weights at path against the heuristic, on fresh traces of
+    every named graph (the training graphs and the held-out ones), as the loop makes it."""
+    import time
+
+    W = load_weights(path)
+    report = {"weights": os.path.basename(path), "learned_min_frontier": LEARNED_MIN_FRONTIER,
+              "meta": json.load(open(path)).get("meta", {}), "train": {}, "held_out": {}}
+    for part, names in (("train", train), ("held_out", held_out)):
+        for name in names:
+            g = _graph_for(name)
+            t0 = time.time()
+            r = collect_rounds(g.offsets, g.adj, repeats=repeats)
+            it = iter(learned_choices(W, r))
+            report[part][name] = {"rounds": len(r), "learned": evaluate(r, lambda q: int(next(it))),
+                                  "heuristic": evaluate(r, lambda q: heuristic_choice(q["frontier"]))}
+            print(part, name, f"{time.time() - t0:.1f}s", report[part][name], flush=True)
+    if report_path:
+        with open(report_path, "w") as f:
+            json.dump(report, f, indent=1)
+    return report
+
+
 def main(argv=None):
     """python -m paper_1707_02000_amd.tuner --train er4096 rmat20 chunglu20 batch256 --held-out rmat24"""
     import argparse
@@ -214,7 +237,12 @@ def main(argv=None):
     ap.add_argument("--repeats", type=int, default=2)
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
     ap.add_argument("--report", default=None)
+    ap.add_argument("--evaluate", default=None,
+                    help="score these weights on fresh traces of the --train and --held-out graphs "
+                         "instead of training")
     args = ap.parse_args(argv)
+    if args.evaluate:
+        return evaluate_weights(args.evaluate, args.train, args.held_out, args.repeats, args.report)
     train_rounds, report = [], {"train": {}, "held_out": {}}
     for name in args.train:
         g = _graph_for(name)
