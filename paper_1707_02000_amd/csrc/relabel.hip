@@ -236,6 +236,7 @@ truss_status run_relabelled(i32 n, i64 two_m, const i64* off64_in, const i32* of
   work_layout(n, two_m, false, r.regionA, &w2);
   w2.off = r.off2;
   w2.adj = r.adj2;
+  w2.id_order = true;  // new ids increase with (degree, id): the support walk needs no edge ids
   truss_options o2 = opt;
   o2.validate = 0;
   o2.relabel = 0;

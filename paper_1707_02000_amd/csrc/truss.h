@@ -95,6 +95,8 @@ struct Work {
   Ctl* ctl;
   u32* verr;        // validation error bits
   bool no_alloc;    // host side allocates nothing: pageable readbacks, no events or graphs
+  bool id_order;    // vertex ids follow the (degree, id) rank (a graph relabelled by it), so the
+                    // oriented CSR is the upper half of every row and its slot k holds edge k
 };
 
 size_t work_layout(i32 n, i64 two_m, bool off32, void* base, Work* w);

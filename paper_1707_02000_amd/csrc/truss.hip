@@ -128,18 +128,19 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_slots(i32 n, i64 two_m, const i64
 }
 
 // Oriented CSR: the slots flagged above, in their original (sorted-by-id)
-// order; X is the exclusive scan of the flags.
+// order; X is the exclusive scan of the flags.  Edge ids only when asked (with ids
+// in rank order, slot d holds edge d).
 __global__ __launch_bounds__(PKT_BLOCK) void k_orient(i32 n, i64 two_m, const i64* __restrict__ off,
                                                      const i32* __restrict__ adj, const i32* __restrict__ eid,
                                                      const u8* __restrict__ oflag, const i64* __restrict__ X,
                                                      i64* __restrict__ ooff, i32* __restrict__ oadj,
-                                                     i32* __restrict__ oeid) {
+                                                     i32* __restrict__ oeid, int write_eid) {
   const i64 tid = (i64)blockIdx.x * PKT_BLOCK + threadIdx.x, stride = (i64)gridDim.x * PKT_BLOCK;
   for (i64 j = tid; j < two_m; j += stride)
     if (oflag[j]) {
       const i64 d = X[j];
       oadj[d] = adj[j];
-      oeid[d] = eid[j];
+      if (write_eid) oeid[d] = eid[j];
     }
   for (i64 u = tid; u <= n; u += stride) ooff[u] = X[off[u]];
 }
@@ -171,10 +172,19 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_orient(i32 n, i64 two_m, const i6
 // through LDS counters per slot of N+(u), flushed once per u.  Rows longer than
 // SUP_DMAX take a path with binary searches instead.  Vertices come from
 // an atomic work queue in chunks (dynamic scheduling).
+// Edge id of oriented slot k: oeid[k], or k itself when the ids follow the rank
+// (IDENT: the oriented CSR is then the rows' upper halves in edge order), which
+// saves the support walk one of its two loads per entry.
+template <bool IDENT>
+__device__ __forceinline__ i32 oid(const i32* __restrict__ oeid, i64 k) {
+  return IDENT ? (i32)k : oeid[k];
+}
+
 // Long out-row (more than SUP_DMAX entries): one wave per v in N+(u), lanes over
 // N+(v), each w looked up by binary search in N+(u) -- staged sorted in LDS (the
 // hash table's space) when it fits in 2 * SUP_DMAX entries, else in memory; all
 // three edges by global atomics.
+template <bool IDENT>
 __device__ void support_long_row(i32 b_u, i64 b, i32 d, const i64* __restrict__ ooff, const i32* __restrict__ oadj,
                                  const i32* __restrict__ oeid, i32* __restrict__ sw, i32* lds) {
   const bool staged = d <= 2 * SUP_DMAX;
@@ -200,17 +210,18 @@ __device__ void support_long_row(i32 b_u, i64 b, i32 d, const i64* __restrict__ 
         hit = p < b + d && oadj[p] == w;
       }
       if (hit) {
-        atomicAdd(&sw[oeid[p]], SW_ONE);  // edge (u, w)
-        atomicAdd(&sw[oeid[k]], SW_ONE);  // edge (v, w)
+        atomicAdd(&sw[oid<IDENT>(oeid, p)], SW_ONE);  // edge (u, w)
+        atomicAdd(&sw[oid<IDENT>(oeid, k)], SW_ONE);  // edge (v, w)
         ++c_uv;
       }
     }
     c_uv = (i32)wave_sum_i64(c_uv);
-    if (lane == 0 && c_uv) atomicAdd(&sw[oeid[b + i]], c_uv * SW_ONE);  // edge (u, v)
+    if (lane == 0 && c_uv) atomicAdd(&sw[oid<IDENT>(oeid, b + i)], c_uv * SW_ONE);  // edge (u, v)
   }
   __syncthreads();  // the LDS is the next vertex's table
 }
 
+template <bool IDENT>
 __global__ __launch_bounds__(SUP_THREADS) void k_support(i32 n, const i64* __restrict__ ooff,
                                                         const i32* __restrict__ oadj, const i32* __restrict__ oeid,
                                                         i32* __restrict__ sw, i32* __restrict__ queue) {
@@ -231,7 +242,7 @@ __global__ __launch_bounds__(SUP_THREADS) void k_support(i32 n, const i64* __res
       const i32 d = (i32)(ooff[u + 1] - b);
       if (d < 2) continue;
       if (d > SUP_DMAX) {
-        support_long_row(u, b, d, ooff, oadj, oeid, sw, keys);
+        support_long_row<IDENT>(u, b, d, ooff, oadj, oeid, sw, keys);
         continue;
       }
       int tbits = 6;
@@ -279,7 +290,7 @@ __global__ __launch_bounds__(SUP_THREADS) void k_support(i32 n, const i64* __res
           for (int q = 0; q < SUP_UNROLL; ++q) {
             const i64 k = k0 + q * PKT_WAVE;
             wq[q] = k < ve ? oadj[k] : -1;
-            fq[q] = k < ve ? oeid[k] : -1;
+            fq[q] = k < ve ? oid<IDENT>(oeid, k) : -1;
           }
 #pragma unroll
           for (int q = 0; q < SUP_UNROLL; ++q) {
@@ -307,7 +318,7 @@ __global__ __launch_bounds__(SUP_THREADS) void k_support(i32 n, const i64* __res
       }
       __syncthreads();
       for (int i = tid; i < d; i += SUP_THREADS)
-        if (cnt[i]) atomicAdd(&sw[oeid[b + i]], cnt[i] * SW_ONE);
+        if (cnt[i]) atomicAdd(&sw[oid<IDENT>(oeid, b + i)], cnt[i] * SW_ONE);
       __syncthreads();
     }
   }
@@ -488,7 +499,7 @@ truss_status build_edges(const Work& w, hipStream_t s) {
                      w.locnt, w.ebase, w.eid, w.el, w.flag);
   PKT_HIP(scan_launch(ArrayLen<u8>{w.flag, w.two_m}, w.partial, w.X, &w.ctl->scan_arrive, s));
   hipLaunchKernelGGL(k_orient, dim3(grid_for_h(w.two_m)), dim3(PKT_BLOCK), 0, s, n, w.two_m, w.off, w.adj, w.eid,
-                     w.flag, w.X, w.ooff, w.oadj, w.oeid);
+                     w.flag, w.X, w.ooff, w.oadj, w.oeid, w.id_order ? 0 : 1);
   PKT_LAUNCH_CHECK();
   return TRUSS_OK;
 }
@@ -497,8 +508,12 @@ truss_status compute_support(const Work& w, hipStream_t s) {
   // support 0, state ST_ALIVE
   hipLaunchKernelGGL(k_fill_i32, dim3(grid_for_h(w.m, 2048)), dim3(PKT_BLOCK), 0, s, w.sw, w.m, sw_make(0, ST_ALIVE));
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(1), 0, s, &w.ctl->work_queue, (i64)1, 0);
-  hipLaunchKernelGGL(k_support, dim3(SUP_BLOCKS), dim3(SUP_THREADS), 0, s, n_of(w), (const i64*)w.ooff,
-                     (const i32*)w.oadj, (const i32*)w.oeid, w.sw, &w.ctl->work_queue);
+  if (w.id_order)
+    hipLaunchKernelGGL(k_support<true>, dim3(SUP_BLOCKS), dim3(SUP_THREADS), 0, s, n_of(w), (const i64*)w.ooff,
+                       (const i32*)w.oadj, (const i32*)w.oeid, w.sw, &w.ctl->work_queue);
+  else
+    hipLaunchKernelGGL(k_support<false>, dim3(SUP_BLOCKS), dim3(SUP_THREADS), 0, s, n_of(w), (const i64*)w.ooff,
+                       (const i32*)w.oadj, (const i32*)w.oeid, w.sw, &w.ctl->work_queue);
   hipLaunchKernelGGL(k_sum_support, dim3(grid_for_h(w.m, 2048)), dim3(PKT_BLOCK), 0, s, (const i32*)w.sw, w.m,
                      w.ctl);
   PKT_LAUNCH_CHECK();
