@@ -98,6 +98,7 @@ struct PeelArgs {
   const float* mlp;  // cost-model weights (TRUSS_VARIANT_LEARNED) or NULL
   int want_features; // frontier features: 0 never, 1 learned policy (large frontiers), 2 every decision (tracing)
   int multi;         // fused rounds run as one cooperative multi-round launch (k_psl_multi)
+  int lite;          // rounds end in k_decide_lite (no continuation, features or cost model)
 };
 
 __device__ __forceinline__ i32* cur_of(const PeelArgs& a, int sel) { return a.F[sel]; }

@@ -1172,6 +1172,39 @@ __global__ __launch_bounds__(DECIDE_THREADS) void k_decide(PeelArgs a, i64 seq, 
 }
 
 
+// k_decide for runs that need no continuation, no features and no cost model
+// (heuristic or forced launch choices, no trace): the same round end and choice,
+// made by one lane of one wave, with no LDS.
+__global__ __launch_bounds__(PKT_WAVE) void k_decide_lite(PeelArgs a, i64 seq, int publish) {
+  if (threadIdx.x != 0) return;
+  Ctl* ctl = a.ctl;
+  const i32 rd = ctl->round_done;
+  if (!ctl->done && (rd || ctl->choice == CHOICE_NONE)) {
+    if (rd) {
+      ctl_after_sublevel(ctl, ctl->ncurr, ctl->nnext, ctl->sel);
+      ctl->round_done = 0;
+      ctl->choice = CHOICE_NONE;
+    }
+    const i32 nc = ctl->ncurr;
+    if (nc > 0) {
+      const int policy = ctl->policy;
+      int c = heuristic_choice(policy, nc);
+      if (policy == TRUSS_VARIANT_FIXED) {
+        const int f = ctl->force_choice;
+        if (f >= 0 && f < TRUSS_NUM_CHOICES && (!is_fused(f) || nc <= SMALL_FRONTIER)) c = f;
+      }
+      ctl->choice = c;
+      ctl->chosen[c] += 1;
+      for (int k = 0; k < 3; ++k) ctl->mcnt[k] = 0;
+      ctl->variant = (policy == TRUSS_VARIANT_MERGE || c == TRUSS_CHOICE_WIDE_GALLOP) ? TRUSS_VARIANT_MERGE
+                                                                                       : TRUSS_VARIANT_BSEARCH;
+      ctl->feat[0] = log2f(1.f + (float)nc);
+      for (int i = 1; i < 8; ++i) ctl->feat[i] = 0.f;
+    }
+  }
+  if (publish) publish_snap(a, ctl, ctl->snap, seq);
+}
+
 // ---------------------------------------------------------------- host side
 
 namespace pkt {
@@ -1268,6 +1301,15 @@ struct KernelClock {
 #define PIPE_ALONE 0  // 1: the continuation with the pipelined loop too (tuning builds)
 #endif
 
+// The round's decision: the one-lane kernel when the run needs nothing more.
+static inline hipError_t launch_decide(const PeelArgs& a, i64 seq, int publish, hipStream_t s) {
+  if (a.lite)
+    hipLaunchKernelGGL(k_decide_lite, dim3(1), dim3(PKT_WAVE), 0, s, a, seq, publish);
+  else
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a, seq, publish);
+  return hipGetLastError();
+}
+
 // Cooperative launch of the multi-round kernel: every block resident at once, as its
 // grid barrier needs.
 static truss_status launch_multi(PeelArgs a, hipStream_t s) {
@@ -1303,6 +1345,8 @@ PeelArgs peel_args(const Work& w, const truss_options& opt) {
   // keep one launch per round; tracing and single_round time every round on its own)
   a.multi = opt.multi_round != 0 && !opt.single_round && opt.trace == nullptr &&
             (opt.device_loop == 0 || opt.device_loop == 3);
+  a.lite = a.alone_frontier == 0 && a.alone_items == 0 && a.alone_alive == 0 && a.want_features == 0 &&
+           opt.variant != TRUSS_VARIANT_LEARNED;
   return a;
 }
 
@@ -1330,10 +1374,10 @@ static truss_status launch_round(const Work& w, const PeelArgs& a, const Ctl& hc
     hipLaunchKernelGGL(k_scan_count, dim3(G), dim3(PKT_BLOCK), 0, s, a, w.partial, w.bmin, scan_bits(w));
     hipLaunchKernelGGL(k_scan_write, dim3(G), dim3(PKT_BLOCK), 0, s, a, (const i64*)w.partial,
                        (const u32*)scan_bits(w));
-    hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a, (i64)0, 0);
+    PKT_HIP(launch_decide(a, 0, 0, s));
   } else if (hc.choice == CHOICE_NONE) {
     *kind = 0;
-    hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a, (i64)0, 0);
+    PKT_HIP(launch_decide(a, 0, 0, s));
   } else if (hc.choice == TRUSS_CHOICE_FUSED || hc.choice == TRUSS_CHOICE_FUSED_NARROW) {
     *kind = 1;
     if (a.multi && hc.choice == TRUSS_CHOICE_FUSED) {
@@ -1343,15 +1387,15 @@ static truss_status launch_round(const Work& w, const PeelArgs& a, const Ctl& hc
       const int blocks = hc.choice == TRUSS_CHOICE_FUSED ? FUSED_BLOCKS : FUSED_NARROW_BLOCKS;
       hipLaunchKernelGGL(k_psl_small, dim3(blocks), dim3(SMALL_THREADS), 0, s, a);
     }
-    hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a, (i64)0, 0);
+    PKT_HIP(launch_decide(a, 0, 0, s));
   } else if (hc.choice == TRUSS_CHOICE_WAVE) {
     *kind = 3;
     hipLaunchKernelGGL(k_psl_wave, dim3(WIDE_BLOCKS), dim3(WIDE_THREADS), 0, s, a);
-    hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a, (i64)0, 0);
+    PKT_HIP(launch_decide(a, 0, 0, s));
   } else if (hc.choice == TRUSS_CHOICE_HASH) {
     *kind = 4;
     hipLaunchKernelGGL(k_psl_hash, dim3(HASH_BLOCKS), dim3(PKT_WAVE), 0, s, a);
-    hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a, (i64)0, 0);
+    PKT_HIP(launch_decide(a, 0, 0, s));
   } else {
     *kind = 2;
     // level 0: frontier edges lie in no triangle, nothing to intersect or scan
@@ -1361,7 +1405,7 @@ static truss_status launch_round(const Work& w, const PeelArgs& a, const Ctl& hc
     if (timed) PKT_HIP(prof->mark(s));
     hipLaunchKernelGGL(k_psl_bsearch, dim3(blocks), dim3(WIDE_THREADS), 0, s, a, (const i64*)w.X);
     if (timed) PKT_HIP(prof->mark(s));
-    hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a, (i64)0, 0);
+    PKT_HIP(launch_decide(a, 0, 0, s));
   }
   PKT_LAUNCH_CHECK();
   return TRUSS_OK;
@@ -1373,13 +1417,13 @@ static truss_status launch_round(const Work& w, const PeelArgs& a, const Ctl& hc
 // reading anything.  Launches whose gate is closed return at once.  The first
 // k_decide ends the previous step's wide round.
 static truss_status enqueue_step(const Work& w, const PeelArgs& a, int G, hipStream_t s, KernelClock* prof) {
-  hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a, (i64)0, 0);
+  PKT_HIP(launch_decide(a, 0, 0, s));
   hipLaunchKernelGGL(k_scan_count, dim3(G), dim3(PKT_BLOCK), 0, s, a, w.partial, w.bmin, scan_bits(w));
   hipLaunchKernelGGL(k_scan_write, dim3(G), dim3(PKT_BLOCK), 0, s, a, (const i64*)w.partial,
                        (const u32*)scan_bits(w));
-  hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a, (i64)0, 0);
+  PKT_HIP(launch_decide(a, 0, 0, s));
   hipLaunchKernelGGL(k_psl_small, dim3(FUSED_BLOCKS), dim3(SMALL_THREADS), 0, s, a);
-  hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a, (i64)0, 0);
+  PKT_HIP(launch_decide(a, 0, 0, s));
   PKT_HIP((scan_launch<WideLen, true>(WideLen{a}, w.partial, w.X, &w.ctl->scan_arrive, s)));
   if (prof) PKT_HIP(prof->mark(s));
   hipLaunchKernelGGL(k_psl_bsearch, dim3(WIDE_BLOCKS), dim3(WIDE_THREADS), 0, s, a, (const i64*)w.X);
@@ -1444,7 +1488,7 @@ static truss_status enqueue_seq(const Work& w, const PeelArgs& a, int kind, int 
     hipLaunchKernelGGL(k_psl_bsearch, dim3(blocks), dim3(WIDE_THREADS), 0, s, a, (const i64*)w.X);
     if (prof) PKT_HIP(prof->mark(s));
   }
-  hipLaunchKernelGGL(k_decide, dim3(1), dim3(DECIDE_THREADS), 0, s, a, seq, 1);
+  PKT_HIP(launch_decide(a, seq, 1, s));
   PKT_LAUNCH_CHECK();
   return TRUSS_OK;
 }
