@@ -504,6 +504,53 @@ __device__ void lds_items(const PeelArgs& a, const Csr& c, const i32* curr, i32 
   }
 }
 
+// Item g of a small round taken by a group of G lanes (rounds with at most one item
+// per group over the grid; search variant): the entry's place in the longer row found
+// G ways at a time -- G evenly spaced entries of the range loaded at once, their
+// ballot against the entry narrowing it G-fold -- instead of one lane's binary
+// search, so the chain of dependent loads is about log_G of the row length long
+// instead of log2.  The group's first lane applies the decrement rule; x0, x1 as
+// psl_item_rows.  Called by all G lanes of the group with the same g.
+template <int G>
+__device__ void group_item(const PeelArgs& a, const Csr& c, const EdgeRows& er, const i64* P, i32 nc, i64 g, i32 l,
+                           i32 r, i32& x0, i32& x1) {
+  const int lane = lane_id(), k = lane & (G - 1), shift = lane & (PKT_WAVE - G);  // shift: the group's first lane
+  const u64 gmask = (G == PKT_WAVE) ? ~0ull : (((1ull << G) - 1ull) << shift);
+  const i64 i = upper_bound_dev(P, (i64)0, (i64)nc + 1, g) - 1;
+  const i64 j = er.sb[i] + (g - P[i]);
+  const i32 es = c.eid[j];
+  const i32 ws = a.sw[es];
+  if (is_processed(sw_st(ws), r)) return;
+  const i32 w = c.adj[j];
+  const i64 le = er.lb[i] + er.L[i];
+  // entries before lo are below w, entries from hi on are not
+  i64 lo = er.lb[i], hi = le;
+  while (hi - lo > G) {
+    const i64 step = (hi - lo + G - 1) / G;
+    const i64 q = lo + (i64)k * step;
+    const i32 v = q < hi ? c.adj[q] : INT_MAX;
+    const int below = __popcll(__ballot(v < w) & gmask);  // samples below w: a prefix of the group
+    const i64 nhi = min(lo + (i64)below * step, hi);
+    if (below > 0) lo += (i64)(below - 1) * step + 1;
+    hi = nhi;
+  }
+  const i32 v = lo + k < hi ? c.adj[lo + k] : INT_MAX;
+  const i64 p = lo + __popcll(__ballot(v < w) & gmask);  // first entry not below w
+  if (k != 0 || p >= le || c.adj[p] != w) return;
+  const i32 eo = c.eid[p];
+  const i32 wo = a.sw[eo];
+  if (is_processed(sw_st(wo), r)) return;
+  psl_tri(es, ws, eo, wo, er.e1[i], l, r, a.sw, a.order, a.owner_higher, x0, x1);
+}
+
+// Items of a small round by groups of G lanes, one item per group (total <= groups).
+template <int G>
+__device__ __forceinline__ void group_items(const PeelArgs& a, const Csr& c, const EdgeRows& er, const i64* P, i32 nc,
+                                            i64 total, i32 l, i32 r, i32& x0, i32& x1) {
+  const i64 g = ((i64)blockIdx.x * blockDim.x + threadIdx.x) / G;
+  if (g < total) group_item<G>(a, c, er, P, nc, g, l, r, x0, x1);
+}
+
 // Snapshot of the control block shared through LDS by one block.
 struct CtlView {
   i32 done, ncurr, level, sel, csel, nalive, asel, variant, choice, r, nprev, round_done;
@@ -816,8 +863,24 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_psl_small(PeelArgs a) {
   if (threadIdx.x == 0) ba.n = 0;  // visible after the prefix's barrier
   mark_prev(a, sel, v.r, v.nprev, (i64)blockIdx.x * SMALL_THREADS + threadIdx.x, (i64)nblk * SMALL_THREADS);
   const i64 total = lds_work_prefix<SMALL_THREADS>(a, c, curr, nc, l, v.variant, P, tmp, &er);
-  lds_items<SMALL_THREADS>(a, c, curr, nc, l, r, v.variant, P, total, (i64)blockIdx.x * SMALL_THREADS,
-                           (i64)nblk * SMALL_THREADS, next, &er, &ba);
+  // few items: a group of lanes per item, as wide as the grid allows (the group
+  // searches G ways at a time); otherwise one lane per item
+  const i64 lanes = (i64)nblk * SMALL_THREADS;
+  if (v.variant == TRUSS_VARIANT_BSEARCH && total * 8 <= lanes) {
+    i32 x0 = -1, x1 = -1;
+    if (total * 64 <= lanes)
+      group_items<64>(a, c, er, P, nc, total, l, r, x0, x1);
+    else if (total * 32 <= lanes)
+      group_items<32>(a, c, er, P, nc, total, l, r, x0, x1);
+    else if (total * 16 <= lanes)
+      group_items<16>(a, c, er, P, nc, total, l, r, x0, x1);
+    else
+      group_items<8>(a, c, er, P, nc, total, l, r, x0, x1);
+    ba.add(x0, x1, next, &ctl->nnext);
+  } else {
+    lds_items<SMALL_THREADS>(a, c, curr, nc, l, r, v.variant, P, total, (i64)blockIdx.x * SMALL_THREADS,
+                             (i64)nblk * SMALL_THREADS, next, &er, &ba);
+  }
   ba.flush(next, &ctl->nnext);
 }
 

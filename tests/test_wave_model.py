@@ -141,3 +141,48 @@ def test_hash_clusters_and_large_ids():
     L = np.array(sorted({(k << 23) for k in range(200)} | {2**31 - 2 - k for k in range(56)}), np.int64)
     S = L[::3].copy()
     assert sorted(hash_model(S, L)) == truth(S, L)
+
+
+# ---- the grouped search of a small round's item (group_item in csrc/peel.hip)
+
+def group_search(adj, lb, le, w, G):
+    """G lanes find the first entry of adj[lb:le] not below w: G evenly spaced entries
+    of the open range per step, their count below w narrows it; then one last load of
+    at most G entries.  Returns (position, steps)."""
+    def gather(q, hi):
+        out = np.full(G, BIG, np.int64)
+        m = q < hi
+        out[m] = adj[q[m]]
+        return out
+
+    lo, hi, steps = lb, le, 0
+    while hi - lo > G:
+        step = (hi - lo + G - 1) // G
+        v = gather(lo + np.arange(G) * step, hi)
+        below = int(np.count_nonzero(v < w))
+        assert np.all(v[:below] < w) and np.all(v[below:] >= w)  # a prefix of the lanes
+        nhi = min(lo + below * step, hi)
+        if below > 0:
+            lo += (below - 1) * step + 1
+        hi = nhi
+        steps += 1
+    v = gather(lo + np.arange(G), hi)
+    return lo + int(np.count_nonzero(v < w)), steps
+
+
+@pytest.mark.parametrize("G", [8, 16, 32, 64])
+def test_group_search_is_a_lower_bound(G):
+    rng = np.random.default_rng(G)
+    for t in range(1500):
+        L = int(rng.integers(0, 3000)) if t % 3 else int(rng.integers(0, 2 * G + 3))
+        row = np.sort(rng.choice(100_000, size=L, replace=False)).astype(np.int64)
+        pad = int(rng.integers(0, 5))
+        adj = np.concatenate([np.sort(rng.integers(0, 100_000, pad)), row,
+                              np.sort(rng.integers(0, 100_000, pad))]).astype(np.int64)
+        w = int(rng.choice(row)) if (L and t % 2) else int(rng.integers(0, 100_001))
+        p, steps = group_search(adj, pad, pad + L, w, G)
+        assert p == pad + int(np.searchsorted(row, w))
+        bound = 0
+        while G ** (bound + 1) < L:
+            bound += 1
+        assert steps <= bound + 1
