@@ -277,6 +277,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the learned / R-MAT s24 / batched comparison fields")
+    ap.add_argument("--profile-batch", action="store_true",
+                    help="only decompose the 4096-graph batch once as one union and once with the persistent "
+                         "launch (validation off), for a kernel-time profile of the batched modes")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (5 times), to scale "
                          "the FETCH_SIZE / WRITE_SIZE hardware counters")
@@ -290,6 +293,22 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": src.numel() * 4, "copies": 5}))
+        return
+    if args.profile_batch:
+        import torch
+
+        import graphgen as gg
+        import paper_1707_02000_amd as pkt
+
+        b = gg.workload("batch4096", seed=1)
+        dev = [torch.from_numpy(x).cuda() for x in (b.vtx_off, b.adj_off, b.offsets, b.adj)]
+        out = {}
+        for mode in ("union", "persistent"):
+            t0 = time.perf_counter()
+            pkt.truss_decompose_batched(*dev, validate=False, mode=mode)
+            torch.cuda.synchronize()
+            out[mode + "_s"] = time.perf_counter() - t0
+        print(json.dumps({"graphs": b.num_graphs, "m": b.total_m, **out}))
         return
     if args.gpus != 1:
         print(f"bench.py: the library runs one decomposition on one GPU (got --gpus {args.gpus}); "
