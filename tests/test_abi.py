@@ -86,6 +86,26 @@ def test_workspace_bytes_host_only(lib):
     assert ei.value.name == "TRUSS_E_RANGE"
 
 
+def test_relabel_option_and_its_workspace(lib):
+    # host only: relabel = 1 (auto, default) and 2 (always) need the relabelled CSR and the
+    # permutation on top of the decomposition's own arrays (about 16 B per edge and 40 per
+    # vertex); 0 does not; other values are rejected before any device work
+    import paper_1707_02000_amd as pkt
+
+    n, two_m = 100_000, 4_000_000
+    plain = pkt.workspace_bytes(n, two_m, pkt.make_options(relabel="off"))
+    auto = pkt.workspace_bytes(n, two_m)
+    always = pkt.workspace_bytes(n, two_m, pkt.make_options(relabel="always"))
+    assert auto == always == pkt.workspace_bytes(n, two_m, pkt.make_options(relabel=True))
+    assert plain == pkt.workspace_bytes(n, two_m, pkt.make_options(relabel=False))
+    assert auto - plain >= 16 * (two_m // 2) + 36 * n
+    assert pkt.relabel_mode("auto") == 1 and pkt.relabel_mode(True) == 2 and pkt.relabel_mode(False) == 0
+    o = pkt.default_options()
+    o.relabel = 3
+    assert lib.truss_decompose(4, None, None, None, None, 0, ctypes.byref(o), None, None) == 1
+    assert b"relabel" in lib.truss_last_error()
+
+
 def test_strerror_covers_every_status(lib):
     for code in range(8):
         assert lib.truss_strerror(code)
