@@ -21,8 +21,6 @@
 // Workspace: region A (the decomposition's own layout, which the order and relabel
 // steps use as scratch before the decomposition starts), then the relabelled CSR,
 // the permutation and the map's arrays.
-#include <string.h>
-
 #include "scan.h"
 #include "truss.h"
 
@@ -171,7 +169,6 @@ truss_status run_relabelled(i32 n, i64 two_m, const i64* off64_in, const i32* of
                             void* ws, const truss_options& opt, truss_stats* stats, hipStream_t s) {
   RelabelWork r;
   relabel_layout(n, two_m, ws, &r);
-  const i64 m = two_m / 2;
   const bool timed = stats != nullptr;
   hipEvent_t ev[5];
   if (timed)
