@@ -171,7 +171,9 @@ __global__ __launch_bounds__(PKT_BLOCK) void k_orient(i32 n, i64 two_m, const i6
 // to its three edges: edge (v, w) by a global atomic, edges (u, v) and (u, w)
 // through LDS counters per slot of N+(u), flushed once per u.  Rows longer than
 // SUP_DMAX take a path with binary searches instead.  Vertices come from
-// an atomic work queue in chunks (dynamic scheduling).
+// an atomic work queue in chunks (dynamic scheduling); with ids in rank order (a
+// relabelled graph) the queue runs from the highest id down, so the vertices with
+// the most work start first and the light ones fill the tail.
 // Edge id of oriented slot k: oeid[k], or k itself when the ids follow the rank
 // (IDENT: the oriented CSR is then the rows' upper halves in edge order), which
 // saves the support walk one of its two loads per entry.
@@ -237,7 +239,8 @@ __global__ __launch_bounds__(SUP_THREADS) void k_support(i32 n, const i64* __res
     __syncthreads();
     if (u0 >= n) break;
     const i32 u1 = min(n, u0 + SUP_CHUNK);
-    for (i32 u = u0; u < u1; ++u) {
+    for (i32 uq = u0; uq < u1; ++uq) {
+      const i32 u = IDENT ? n - 1 - uq : uq;  // rank order: the heavy vertices first
       const i64 b = ooff[u];
       const i32 d = (i32)(ooff[u + 1] - b);
       if (d < 2) continue;
