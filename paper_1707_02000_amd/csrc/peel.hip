@@ -1000,7 +1000,7 @@ struct WideLen {
 // spaced entries of the longer row in LDS (the whole row when it is at most
 // NSAMP long, as for most of the work on skewed graphs); a lane finds the bracket of its entry among the samples in LDS and
 // binary-searches only that bracket, at most `step` contiguous entries, in
-// memory.  Consecutive tiles of one edge keep the staged samples.
+// memory.  A block's next tile of the same edge keeps the staged samples.
 #ifndef NSAMP
 #define NSAMP 4096
 #endif
@@ -1071,8 +1071,10 @@ __device__ void tile_one_edge(const PeelArgs& a, const Csr& c, const i32* curr, 
 
 // Wide round: one thread per intersection item over the whole grid, items
 // located through the device-wide work prefix P (not read at level 0, where
-// there are no items); k_decide follows and ends the round.  Each block takes a
-// contiguous range of tiles of PKT_BLOCK items; a tile inside one edge's items
+// there are no items); k_decide follows and ends the round.  Block b takes tiles
+// of PKT_BLOCK items b, b + blocks, b + 2 blocks, ... (strided: the items' cost
+// grows along the frontier, whose edges come in edge-id order, so fixed contiguous
+// ranges would leave the last blocks with the dearest tiles); a tile inside one edge's items
 // takes the staged-sample path (tile_one_edge), any other tile locates every
 // item's edge and searches the longer row directly.  TRUSS_CHOICE_WIDE_NARROW
 // uses the first WIDE_NARROW_BLOCKS blocks.  Kept lean: its register count sets
@@ -1111,9 +1113,7 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_psl_bsearch(PeelArgs a, const 
     ba.n = 0;
   }
   const i64 tiles = (total + WIDE_THREADS - 1) / WIDE_THREADS;
-  const i64 per = (tiles + nblk - 1) / nblk;
-  const i64 t_end = min(tiles, ((i64)blockIdx.x + 1) * per);
-  for (i64 tile = (i64)blockIdx.x * per; tile < t_end; ++tile) {
+  for (i64 tile = blockIdx.x; tile < tiles; tile += nblk) {
     const i64 base = tile * WIDE_THREADS;
     if (threadIdx.x == 0) sp[0] = upper_bound_dev(P, (i64)0, npairs + 1, base) - 1;
     if (threadIdx.x == PKT_WAVE)
