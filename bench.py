@@ -102,10 +102,12 @@ def cpu_baseline(sample_name="rmat17"):
            "sample": f"{sample_name}: R-MAT scale {sample_name[4:]}, edge factor 16, same (a,b,c,d) recipe, seed 1 "
                      f"(m={d['m']}); one full serial decomposition on one pinned core, {d['s']:.1f} s",
            "host_nproc": os.cpu_count(), "host_affinity": len(os.sched_getaffinity(0)), "cpu_model": _cpu_model()}
-    gold = os.path.join(ROOT, "tests", "golden", "rmat20.json")
-    if os.path.exists(gold):  # the stored full-size run, as context (another host, same oracle)
-        rec = json.load(open(gold))
-        out["context_rmat20_oracle"] = {"seconds": rec["oracle_seconds"], "edges_per_s": rec["m"] / rec["oracle_seconds"]}
+    for name in ("rmat20", "rmat24"):  # the stored full-size runs, as context (another host, same oracle)
+        gold = os.path.join(ROOT, "tests", "golden", f"{name}.json")
+        if os.path.exists(gold):
+            rec = json.load(open(gold))
+            out[f"context_{name}_oracle"] = {"seconds": rec["oracle_seconds"],
+                                             "edges_per_s": rec["m"] / rec["oracle_seconds"]}
     return out
 
 
