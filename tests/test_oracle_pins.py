@@ -256,3 +256,42 @@ def test_malformed_csr_is_rejected():
         assert not oracle.check_csr(g), (off, adj)
         with pytest.raises(oracle.OracleInputError):
             oracle.truss(g)
+
+
+# ---- the stored full-size oracle records (tests/golden/*.json, *.txt) are self-consistent
+
+def _full_size_records():
+    import json
+
+    for f in sorted(os.listdir(GOLDEN)):
+        if f.endswith(".json"):
+            rec = json.load(open(os.path.join(GOLDEN, f)))
+            if "trussness_sha256" in rec:
+                yield f, rec
+
+
+@pytest.mark.parametrize("name,rec", list(_full_size_records()), ids=lambda x: x if isinstance(x, str) else "")
+def test_stored_records_are_consistent(name, rec):
+    """Every stored run: the trussness histogram covers all m edges, has no mass below 2 (every
+    edge is in the 2-truss), ends at t_max, and a graph with triangles has t_max >= 3 (and none
+    means t_max = 2); the digests are sha256 hex strings."""
+    h = rec["histogram"]
+    assert sum(h) == rec["m"] and len(h) == rec["t_max"] + 1 and h[-1] > 0
+    assert h[0] == 0 and h[1] == 0
+    assert (rec["triangles"] > 0) == (rec["t_max"] >= 3)
+    for k in ("csr_sha256", "trussness_sha256", "support_sha256"):
+        assert len(rec[k]) == 64 and int(rec[k], 16) >= 0
+
+
+def test_stored_batch_records_are_consistent():
+    """The per-graph batch records: one line per graph, in order, each with a sha256 digest and
+    t_max >= 2 for a graph with edges."""
+    for f in ("batch64.txt", "batch4096.txt"):
+        path = os.path.join(GOLDEN, f)
+        if not os.path.exists(path):
+            continue
+        rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+        assert [int(r[0]) for r in rows] == list(range(len(rows)))
+        for g, n, m, t, h in rows:
+            assert int(n) > 0 and int(m) >= 0 and len(h) == 64
+            assert (int(m) == 0) or int(t) >= 2
