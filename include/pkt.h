@@ -238,7 +238,8 @@ truss_status truss_decompose(int32_t n, const int64_t* offsets, const int32_t* a
                              truss_stats* stats, void* stream);
 
 /* Same as truss_decompose for int32 offsets (requires offsets[n] <= 2^31 - 1).
- * Needs truss_workspace_bytes(n, two_m) + 8 * (n + 1) bytes, rounded up to 256. */
+ * Needs truss_workspace_bytes(n, two_m, opt) bytes, which include the int64 copy of
+ * the offsets the library makes. */
 truss_status truss_decompose32(int32_t n, const int32_t* offsets, const int32_t* adj, int32_t* trussness,
                                void* workspace, size_t workspace_bytes, const truss_options* opt,
                                truss_stats* stats, void* stream);
@@ -248,8 +249,9 @@ truss_status truss_decompose32(int32_t n, const int32_t* offsets, const int32_t*
  * (serving loops that must not call hipMalloc, harnesses that forbid allocation).
  * The workspace is a static device array of 64 MiB (2^26 bytes) inside the
  * library, one per GPU, held until the process ends: graphs whose
- * truss_workspace_bytes(n, offsets[n]) + 8 * (n + 1) exceeds it are rejected with
- * TRUSS_E_WORKSPACE (about 700 000 edges for sparse graphs).  The library calls
+ * truss_workspace_bytes(n, offsets[n]) under relabel = 0 exceeds it are rejected
+ * with TRUSS_E_WORKSPACE (about 700 000 edges for sparse graphs; this entry point
+ * never relabels).  The library calls
  * no hipMalloc, hipFree, hipHostMalloc, event, stream or graph creation here: the
  * loop state is read back into pageable host memory, device_loop 2 and 3 run as 1
  * (device-driven steps), opt->trace and opt->profile are rejected (TRUSS_E_ARG)
